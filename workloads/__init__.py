@@ -1,0 +1,270 @@
+"""Seeded synthetic hybrid-SAT instances and evaluation points.
+
+This module only draws random structure and random points. It holds none of
+the method's arithmetic, so both the HIP library's tests and the CPU oracle
+can take their inputs from it.
+
+Conventions (as in the paper's Preliminaries and its restart examples):
+  * literals are DIMACS-style signed 1-based integers: ``+v`` is x_v and
+    ``-v`` is its negation, whose value in [-1, 1] is ``-x_v``;
+  * kinds: 0 = OR (CNF clause), 1 = XOR, 2 = at-least-t cardinality;
+  * params: XOR parity bit p (1 = an odd number of true literals is
+    required), cardinality threshold t, ignored for OR;
+  * points are stored variable-major, ``x[n][B]``, restarts contiguous.
+
+Workload shapes follow the random formulas of the paper's benchmark
+appendix (random cardinality formulas: literals all positive or all
+negative with probability 1/2; the RQ1 gradient-timing formulas) and the
+configurations this library is measured on (random 3-SAT at ratio 4.26, a
+mixed OR/XOR/cardinality instance, and a large mixed instance).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+KIND_OR, KIND_XOR, KIND_CARD = 0, 1, 2
+KIND_NAMES = {KIND_OR: "or", KIND_XOR: "xor", KIND_CARD: "card"}
+
+
+@dataclass
+class Instance:
+    n_vars: int
+    con_ptr: np.ndarray            # int64 [m+1]
+    lits: np.ndarray               # int32 [nnz], signed 1-based
+    kinds: np.ndarray              # int32 [m]
+    params: np.ndarray             # int32 [m]
+    weights: Optional[np.ndarray] = None   # float32 [m] or None (all ones)
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return int(self.kinds.shape[0])
+
+    @property
+    def nnz(self) -> int:
+        return int(self.lits.shape[0])
+
+    def lengths(self) -> np.ndarray:
+        return np.diff(self.con_ptr).astype(np.int64)
+
+    def constraint(self, c: int):
+        a, b = int(self.con_ptr[c]), int(self.con_ptr[c + 1])
+        return int(self.kinds[c]), int(self.params[c]), self.lits[a:b]
+
+    def weights_or_ones(self) -> np.ndarray:
+        if self.weights is None:
+            return np.ones(self.m, dtype=np.float32)
+        return np.asarray(self.weights, dtype=np.float32)
+
+    def save(self, path: str) -> None:
+        np.savez(path, n_vars=np.int64(self.n_vars), con_ptr=self.con_ptr,
+                 lits=self.lits, kinds=self.kinds, params=self.params,
+                 weights=(self.weights if self.weights is not None
+                          else np.zeros(0, np.float32)))
+
+    @staticmethod
+    def load(path: str) -> "Instance":
+        z = np.load(path, allow_pickle=False)
+        w = z["weights"]
+        return Instance(int(z["n_vars"]), z["con_ptr"], z["lits"], z["kinds"],
+                        z["params"], w if w.size else None)
+
+
+# --------------------------------------------------------------------------
+# building blocks
+# --------------------------------------------------------------------------
+
+def _distinct_rows(rng: np.random.Generator, n: int, rows: int, k: int) -> np.ndarray:
+    """rows x k matrix of variable indices in [0, n), distinct within a row."""
+    if k > n:
+        raise ValueError(f"cannot draw {k} distinct variables out of {n}")
+    out = rng.integers(0, n, size=(rows, k), dtype=np.int64)
+    if k == 1:
+        return out
+    while True:
+        s = np.sort(out, axis=1)
+        bad = np.nonzero((s[:, 1:] == s[:, :-1]).any(axis=1))[0]
+        if bad.size == 0:
+            return out
+        out[bad] = rng.integers(0, n, size=(bad.size, k), dtype=np.int64)
+
+
+def _draw_group(rng, n, count, kmin, kmax, sign_mode):
+    """Draw `count` constraints with lengths U{kmin..kmax}.
+
+    sign_mode: 'bernoulli' (each literal negated with prob. 1/2),
+               'positive' (no negations),
+               'uniform_block' (all literals of a constraint share one sign,
+                                negative with prob. 1/2).
+    Returns (lengths[count], list of signed-literal arrays in draw order).
+    """
+    lens = rng.integers(kmin, kmax + 1, size=count)
+    rows = [None] * count
+    for k in np.unique(lens):
+        idx = np.nonzero(lens == k)[0]
+        vars_ = _distinct_rows(rng, n, idx.size, int(k)) + 1
+        if sign_mode == "bernoulli":
+            neg = rng.random(vars_.shape) < 0.5
+        elif sign_mode == "positive":
+            neg = np.zeros(vars_.shape, dtype=bool)
+        elif sign_mode == "uniform_block":
+            neg = np.repeat(rng.random((idx.size, 1)) < 0.5, int(k), axis=1)
+        else:
+            raise ValueError(sign_mode)
+        signed = np.where(neg, -vars_, vars_).astype(np.int32)
+        for r, c in enumerate(idx):
+            rows[c] = signed[r]
+    return lens, rows
+
+
+def assemble(n_vars: int, groups, name: str = "", weights=None, meta=None) -> Instance:
+    """groups: list of (kind, params[count], rows list). Constraints keep the order given."""
+    kinds, params, rows = [], [], []
+    for kind, prm, rws in groups:
+        kinds.append(np.full(len(rws), kind, dtype=np.int32))
+        params.append(np.asarray(prm, dtype=np.int32))
+        rows.extend(rws)
+    lens = np.array([len(r) for r in rows], dtype=np.int64)
+    con_ptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum(lens, out=con_ptr[1:])
+    lits = (np.concatenate(rows).astype(np.int32) if rows else np.zeros(0, np.int32))
+    return Instance(n_vars, con_ptr, lits, np.concatenate(kinds) if kinds else
+                    np.zeros(0, np.int32), np.concatenate(params) if params else
+                    np.zeros(0, np.int32), weights, name, meta or {})
+
+
+def random_hybrid(n: int, seed: int, *, n_or=0, or_len=(3, 3), or_signs="bernoulli",
+                  n_xor=0, xor_len=(3, 3), xor_signs="positive",
+                  n_card=0, card_len=(10, 10), card_signs="uniform_block",
+                  card_t="half", weights=None, name="") -> Instance:
+    """Random hybrid formula: OR, XOR and at-least-t groups, in that order.
+
+    card_t: 'half' -> t ~ U{1..floor(len/2)}; 'exact_half' -> t = len // 2;
+            an int -> that threshold for every constraint;
+            a (lo, hi) tuple -> t ~ U{lo..hi} (may leave [1, len]).
+    weights: None, 'uniform' (U[0.5, 1.5]) or an array.
+    """
+    rng = np.random.default_rng(seed)
+    groups = []
+    if n_or:
+        _, rows = _draw_group(rng, n, n_or, or_len[0], or_len[1], or_signs)
+        groups.append((KIND_OR, np.zeros(n_or, np.int32), rows))
+    if n_xor:
+        _, rows = _draw_group(rng, n, n_xor, xor_len[0], xor_len[1], xor_signs)
+        par = rng.integers(0, 2, size=n_xor)
+        groups.append((KIND_XOR, par, rows))
+    if n_card:
+        lens, rows = _draw_group(rng, n, n_card, card_len[0], card_len[1], card_signs)
+        if card_t == "half":
+            t = np.array([rng.integers(1, max(1, L // 2) + 1) for L in lens])
+        elif card_t == "exact_half":
+            t = np.maximum(1, lens // 2)
+        elif isinstance(card_t, tuple):
+            t = rng.integers(card_t[0], card_t[1] + 1, size=n_card)
+        else:
+            t = np.full(n_card, int(card_t))
+        groups.append((KIND_CARD, t, rows))
+    inst = assemble(n, groups, name=name)
+    m = inst.m
+    if isinstance(weights, str) and weights == "uniform":
+        inst.weights = rng.uniform(0.5, 1.5, size=m).astype(np.float32)
+    elif weights is not None:
+        inst.weights = np.asarray(weights, dtype=np.float32)
+    return inst
+
+
+# --------------------------------------------------------------------------
+# named workloads
+# --------------------------------------------------------------------------
+
+def instance_seed(config: int, i: int = 0) -> int:
+    return 1000 * config + i
+
+
+def point_seed(inst_seed: int) -> int:
+    return inst_seed + 500000
+
+
+def config1(seed: int = 1000) -> Instance:
+    """Random 3-SAT, n = 50, m = 213 (clause/variable ratio 4.26)."""
+    return random_hybrid(50, seed, n_or=213, or_len=(3, 3), name="3sat-n50-m213")
+
+
+def config2(seed: int = 2000, weights=None) -> Instance:
+    """Mixed: n = 2000; 8000 OR (len 3..7), 500 XOR (len 3..20, positive
+    literals, random parity), 200 at-least-t (len 10..100, t ~ U{1..len/2},
+    literals all positive or all negative)."""
+    return random_hybrid(2000, seed, n_or=8000, or_len=(3, 7), n_xor=500,
+                         xor_len=(3, 20), n_card=200, card_len=(10, 100),
+                         weights=weights, name="mixed-n2000-m8700")
+
+
+def config3(seed: int = 3000) -> Instance:
+    """Large mixed: n = 100000; 420000 3-SAT + 10000 XOR (len 8..64) +
+    2000 at-least-t (len 128..512, t ~ U{1..len/2})."""
+    return random_hybrid(100000, seed, n_or=420000, or_len=(3, 3), n_xor=10000,
+                         xor_len=(8, 64), n_card=2000, card_len=(128, 512),
+                         name="mixed-n100000-m432000")
+
+
+def config3a(seed: int = 3000) -> Instance:
+    """The 3-SAT part of the large instance alone (n = 100000, m = 420000)."""
+    return random_hybrid(100000, seed, n_or=420000, or_len=(3, 3),
+                         name="3sat-n100000-m420000")
+
+
+def config4(seed: int = 4000) -> Instance:
+    """The mixed n = 2000 shape with weights w ~ U[0.5, 1.5]."""
+    return config2(seed, weights="uniform")
+
+
+RQ1_SHAPES = {
+    # name: (n_xor, xor_len, n_card, card_len)
+    "xor+card": (800, 8, 1, 32),
+    "xor1": (200, 8, 0, 0),
+    "xor2": (400, 16, 0, 0),
+    "xor3": (800, 32, 0, 0),
+    "card1": (0, 0, 50, 8),
+    "card2": (0, 0, 100, 16),
+    "card3": (0, 0, 200, 32),
+}
+
+
+def rq1(name: str, seed: int = 6000, n: int = 1000) -> Instance:
+    """The paper's RQ1 formula shapes (counts and lengths); n and the
+    cardinality thresholds are not given there: n = 1000 and t = len/2."""
+    nx, lx, nc, lc = RQ1_SHAPES[name]
+    return random_hybrid(n, seed, n_xor=nx, xor_len=(lx, lx), n_card=nc,
+                         card_len=(lc, lc), card_t="exact_half", name=name)
+
+
+def points(n: int, B: int, seed: int, dist: str = "uniform",
+           dtype=np.float32) -> np.ndarray:
+    """x[n][B] in [-1, 1].
+
+    dist: 'uniform'      U[-1, 1];
+          'near_corner'  +-0.99 with random signs;
+          'corner'       exact +-1;
+          'mixed_edge'   uniform with 10% exact +-1, 5% exact 0, 5% +-0.99.
+    """
+    rng = np.random.default_rng(seed)
+    if dist == "uniform":
+        x = rng.uniform(-1.0, 1.0, size=(n, B))
+    elif dist == "near_corner":
+        x = np.where(rng.random((n, B)) < 0.5, -0.99, 0.99)
+    elif dist == "corner":
+        x = np.where(rng.random((n, B)) < 0.5, -1.0, 1.0)
+    elif dist == "mixed_edge":
+        x = rng.uniform(-1.0, 1.0, size=(n, B))
+        u = rng.random((n, B))
+        sgn = np.where(rng.random((n, B)) < 0.5, -1.0, 1.0)
+        x = np.where(u < 0.10, sgn, x)
+        x = np.where((u >= 0.10) & (u < 0.15), 0.0, x)
+        x = np.where((u >= 0.15) & (u < 0.20), 0.99 * sgn, x)
+    else:
+        raise ValueError(dist)
+    return np.ascontiguousarray(x.astype(dtype))
