@@ -1,0 +1,233 @@
+/*
+ * ffsat.h -- C ABI of the MI355X library that evaluates the Walsh-expansion
+ * objective of a hybrid SAT formula (OR, XOR and at-least-t constraints) and
+ * its gradient for a batch of restarts, by evaluating elementary symmetric
+ * polynomials at roots of unity, plus the projected step, the exact
+ * round-and-check, the adaptive weights and the weight gradient.
+ *
+ * Paper: "Massively Parallel Continuous Local Search for Hybrid SAT Solving
+ * on GPUs" (Cen, Zhang, Fong, AAAI-24).
+ *
+ * Conventions used by every call
+ *   - Truth values: -1 is True, +1 is False (Sec. "Walsh Expansions of
+ *     Boolean Constraints").  A literal +v has value x_v, a literal -v has
+ *     value -x_v.
+ *   - Points are stored variable-major and restart-contiguous: x[v * B + b]
+ *     for variable v in [0, n) and restart b in [0, B).  The same layout is
+ *     used for the gradient; per-constraint values are con_val[c * B + b].
+ *   - Device buffers are plain device pointers owned by the caller (for
+ *     example torch tensors); the library never frees them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call that takes a stream only enqueues work on it and returns
+ *     without synchronising; kernel faults surface at the caller's next
+ *     synchronisation, as usual for HIP.
+ *   - Every call returns an ffsat_status; 0 is success.  On failure no
+ *     output argument is written and ffsat_last_error() gives a message
+ *     (thread-local).  No C++ exception crosses this interface.
+ *   - A problem is immutable after creation except for its weights.  A plan
+ *     must be used from one host thread and one stream at a time; calls
+ *     that overlap on the device race on the plan's workspace.
+ */
+#ifndef FFSAT_H
+#define FFSAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ffsat_status;
+
+#define FFSAT_OK                  0
+#define FFSAT_E_INVALID_ARG      -1  /* null pointer, bad size, bad option */
+#define FFSAT_E_VAR_RANGE        -2  /* a literal is 0 or |lit| > n_vars */
+#define FFSAT_E_DUP_VAR          -3  /* a variable appears twice in one constraint */
+#define FFSAT_E_EMPTY_CONSTRAINT -4  /* a constraint with no literal */
+#define FFSAT_E_BAD_KIND         -5  /* kind not in {OR, XOR, CARD_GE} */
+#define FFSAT_E_DEVICE_MISMATCH  -6  /* device index invalid or not current */
+#define FFSAT_E_NOMEM            -7  /* device or host allocation failed */
+#define FFSAT_E_HIP              -8  /* a HIP runtime call failed */
+#define FFSAT_E_NONFINITE        -9  /* debug checks: NaN/Inf in an input point */
+#define FFSAT_E_UNSUPPORTED     -10  /* e.g. a constraint longer than the maximum */
+
+/* constraint kinds */
+#define FFSAT_KIND_OR       0   /* clause: at least one literal true            */
+#define FFSAT_KIND_XOR      1   /* parity: #true literals odd (param 1) / even (0) */
+#define FFSAT_KIND_CARD_GE  2   /* at least `param` literals true               */
+
+/* problem flags */
+#define FFSAT_FLAG_FORCE_DFT     1u  /* route OR/XOR through the root-of-unity path too */
+#define FFSAT_FLAG_DEBUG_CHECKS  4u  /* check inputs for NaN/Inf (synchronises) */
+
+/* Longest constraint accepted. */
+#define FFSAT_MAX_CONSTRAINT_LEN 512
+
+typedef struct ffsat_problem ffsat_problem;
+typedef struct ffsat_plan ffsat_plan;
+
+/* Host-side description of a constraint set.  All arrays are host memory
+ * and are copied by ffsat_problem_create; the caller may free them on
+ * return. */
+typedef struct {
+    int32_t n_vars;          /* number of variables n >= 1 */
+    int32_t n_cons;          /* number of constraints m >= 1 */
+    const int64_t *con_ptr;  /* [m+1], con_ptr[0] = 0, non-decreasing: literals of
+                                constraint c are lits[con_ptr[c] .. con_ptr[c+1]) */
+    const int32_t *lits;     /* [nnz] signed 1-based literals (DIMACS style) */
+    const int32_t *kinds;    /* [m] FFSAT_KIND_* */
+    const int32_t *params;   /* [m] XOR parity bit / CARD threshold t / ignored for OR.
+                                t <= 0 makes the constraint always true, t > k never. */
+    const float *weights;    /* [m] initial weights w_c, or NULL for all ones */
+    int32_t device;          /* HIP device index; must be the current device */
+    int32_t fp64_min_len;    /* root-of-unity products of constraints with at least
+                                this many literals run in FP64 in ffsat_eval
+                                (0 = default 257) */
+    uint32_t flags;          /* FFSAT_FLAG_* */
+} ffsat_problem_desc;
+
+typedef struct {
+    int32_t n_vars, n_cons;
+    int64_t nnz;
+    int32_t max_len;
+    int32_t n_bins_f32;      /* kernel bins of the FP32 evaluation */
+    int32_t n_bins_f64;      /* kernel bins of the FP64 evaluation */
+    int32_t device;
+    int64_t device_bytes;    /* device memory held by the problem */
+} ffsat_problem_info;
+
+typedef struct {
+    int32_t autotune;        /* 1: time tile shapes per bin at plan creation */
+    int32_t use_graphs;      /* 1: ffsat_run_steps replays a captured hipGraph */
+    const char *tune_cache;  /* JSON file for tuned shapes (NULL = in memory only) */
+    int32_t reserved[8];
+} ffsat_plan_opts;
+
+/* ---- errors ------------------------------------------------------------- */
+
+/* Static string for a status code. */
+const char *ffsat_status_string(ffsat_status s);
+/* Message of the last failing call on this host thread ("" if none). */
+const char *ffsat_last_error(void);
+/* Library version string. */
+const char *ffsat_version(void);
+
+/* ---- problem: "load constraint set" (Def. 3's constraint set C) ---------- */
+
+/* Validates and copies a constraint set to the device: CSR of literals,
+ * variable-major transpose, length/kind bins, and the conjugated
+ * coefficients of every distinct (kind, length, param) computed in FP64
+ * (Eq. inverse, step iii preprocessing).  Validation errors (VAR_RANGE,
+ * DUP_VAR, EMPTY_CONSTRAINT, BAD_KIND, UNSUPPORTED, INVALID_ARG) are
+ * reported before any device call.  *out is written only on success. */
+ffsat_status ffsat_problem_create(const ffsat_problem_desc *d, ffsat_problem **out);
+/* Frees the problem (NULL is allowed).  The caller must have synchronised
+ * work that uses it. */
+ffsat_status ffsat_problem_destroy(ffsat_problem *p);
+ffsat_status ffsat_problem_info_get(const ffsat_problem *p, ffsat_problem_info *info);
+
+/* Weights w_c of Def. 3, original constraint order, [m] floats.  on_device
+ * selects whether `w` is a device or a host pointer.  Enqueued on stream. */
+ffsat_status ffsat_set_weights(ffsat_problem *p, const float *w, int32_t on_device, void *stream);
+ffsat_status ffsat_get_weights(const ffsat_problem *p, float *w, int32_t on_device, void *stream);
+
+/* ---- plan: a batch size B and its workspace ------------------------------ */
+
+/* Binds the batch size B >= 1 and allocates the workspace (per-literal slot
+ * buffer of nnz*B values, objective partials).  opts may be NULL (no
+ * autotuning, graphs on).  *out is written only on success. */
+ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffsat_plan_opts *opts,
+                               ffsat_plan **out);
+ffsat_status ffsat_plan_destroy(ffsat_plan *plan);
+/* Runs the tile-shape autotuner now (synchronises the stream). */
+ffsat_status ffsat_plan_tune(ffsat_plan *plan, void *stream);
+/* Writes a JSON description of the bins and their tile shapes into buf
+ * (truncated to len-1 characters, always NUL-terminated). */
+ffsat_status ffsat_plan_describe(const ffsat_plan *plan, char *buf, size_t len);
+
+/* Kernel timing: while on, every evaluation-kernel launch and every
+ * reduction launch made by ffsat_eval / ffsat_eval_f64 / ffsat_run_steps
+ * (eager, not graph replays) is bracketed by HIP events on the caller's
+ * stream.  ffsat_plan_profile_read synchronises on those events and writes
+ * JSON {"kernels": [{"io", "bin", "launches", "total_ms", "avg_ms"}]} into
+ * buf (truncated to len-1, NUL-terminated); reset != 0 clears the sums. */
+ffsat_status ffsat_plan_profile(ffsat_plan *plan, int32_t on);
+ffsat_status ffsat_plan_profile_read(ffsat_plan *plan, int32_t reset, char *buf, size_t len);
+
+/* ---- objective and gradient at a batch of points (Def. 3, Alg. 2) ------- */
+
+/* For every restart b with x_b = x[. * B + b] in [-1,1]^n (device, [n][B]):
+ *   F[b]           = sum_c w_c WE_c(x_b)          (optional, device [B])
+ *   grad[v*B+b]    = dF/dx_v at x_b               (optional, device [n][B])
+ *   con_val[c*B+b] = WE_c(x_b), unweighted        (optional, device [m][B])
+ * WE_c is evaluated by the three steps of Alg. 2 (affine factors at the
+ * roots of unity, product over literals, dot with the conjugated
+ * coefficients) and differentiated by leave-one-out prefix/suffix products
+ * (Eq. chain); OR and XOR use the transform-free products (App. B).
+ * Computation is FP32 except the root-of-unity products of constraints at
+ * least fp64_min_len long, which run in FP64.  Results are deterministic
+ * (no floating-point atomics).  Points outside [-1,1] are evaluated as
+ * given (the polynomial is defined everywhere). */
+ffsat_status ffsat_eval(ffsat_plan *plan, const float *x, float *F, float *grad,
+                        float *con_val, void *stream);
+/* Same with double buffers and FP64 computation throughout. */
+ffsat_status ffsat_eval_f64(ffsat_plan *plan, const double *x, double *F, double *grad,
+                            double *con_val, void *stream);
+
+/* ---- projected step (App. A.3, Alg. 5, clip to [-1,1]) ------------------- */
+
+/* In place, elementwise: x <- min(max(fma(-eta_b, grad, x), -1), 1) with
+ * eta_b = eta_B[b] if eta_B != NULL else eta.  x, grad: device [n][B];
+ * eta_B: device [B] or NULL. */
+ffsat_status ffsat_step(ffsat_plan *plan, float *x, const float *grad, const float *eta_B,
+                        float eta, void *stream);
+ffsat_status ffsat_step_f64(ffsat_plan *plan, double *x, const double *grad,
+                            const double *eta_B, double eta, void *stream);
+
+/* T fused iterations of (evaluate gradient, projected step with scalar eta)
+ * on x (device [n][B], in place), replayed from a captured hipGraph when the
+ * plan uses graphs.  F_last (device [B] or NULL) receives the objective at
+ * the point the last step started from. */
+ffsat_status ffsat_run_steps(ffsat_plan *plan, float *x, int32_t T, float eta, float *F_last,
+                             void *stream);
+
+/* ---- round and check (Alg. 1, the certificate test of Thm. 2) ------------ */
+
+/* Rounds every variable (x_v < 0 means True; +0, -0 and NaN mean False) and
+ * checks every constraint exactly in integers.  All outputs are optional
+ * device buffers:
+ *   assign_bits[b * ceil(n/32) + v/32] bit v%32 = variable v is True
+ *   n_sat[b]    = number of satisfied constraints of restart b
+ *   unsat_bits[b * ceil(m/32) + c/32] bit c%32 = constraint c is violated
+ *   U[c]        = number of restarts violating c (the ERWA count U_c). */
+ffsat_status ffsat_round_check(ffsat_plan *plan, const float *x, uint32_t *assign_bits,
+                               int32_t *n_sat, uint32_t *unsat_bits, int32_t *U, void *stream);
+ffsat_status ffsat_round_check_f64(ffsat_plan *plan, const double *x, uint32_t *assign_bits,
+                                   int32_t *n_sat, uint32_t *unsat_bits, int32_t *U, void *stream);
+
+/* ---- adaptive weights (Prop. 3) and the weight gradient ------------------ */
+
+/* In place on the problem's weights: r_c = U_c / max_c U_c (r = 0 when the
+ * maximum is 0) and w_c <- (1 - alpha) w_c + alpha r_c.  U: device [m]. */
+ffsat_status ffsat_erwa_update(ffsat_plan *plan, const int32_t *U, float alpha, void *stream);
+
+/* gw[c] = sum_b gF[b] * con_val[c * B + b]: the gradient of sum_b gF_b F_b
+ * with respect to w_c (F is linear in w, Def. 3).  Device buffers. */
+ffsat_status ffsat_weight_grad(ffsat_plan *plan, const float *con_val, const float *gF,
+                               float *gw, void *stream);
+
+/* ---- host-only helper ---------------------------------------------------- */
+
+/* Conjugated coefficients of one symmetric constraint in the bounded
+ * root-of-unity basis: h[a] = (1/(k+1)) sum_c f(c) exp(-2 pi i a c/(k+1)),
+ * a = 0..floor((k+1)/2), with f(c) = -1 if the constraint holds with c true
+ * literals and +1 otherwise (Eq. inverse, with the Poisson-binomial basis of
+ * this library).  Writes 2*(floor((k+1)/2)+1) doubles (re, im interleaved).
+ * Pure host code: no device call. */
+ffsat_status ffsat_coefficients(int32_t kind, int32_t k, int32_t param, double *h_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFSAT_H */

@@ -1,0 +1,1068 @@
+// Host runtime of the ffsat library: validation, CSR / transpose / bins,
+// conjugated coefficient tables in FP64, plans and their workspace,
+// graph capture of the step loop, the tile-shape autotuner, and every
+// C-ABI entry point declared in include/ffsat.h.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <tuple>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace ffsat;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_last_error;
+
+static ffsat_status fail(ffsat_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIPCHK(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? FFSAT_E_NOMEM : FFSAT_E_HIP,          \
+                        "%s failed: %s", #call, hipGetErrorString(e_));                   \
+    } while (0)
+
+extern "C" const char *ffsat_status_string(ffsat_status s)
+{
+    switch (s) {
+    case FFSAT_OK: return "ok";
+    case FFSAT_E_INVALID_ARG: return "invalid argument";
+    case FFSAT_E_VAR_RANGE: return "literal out of variable range";
+    case FFSAT_E_DUP_VAR: return "variable repeated in a constraint";
+    case FFSAT_E_EMPTY_CONSTRAINT: return "empty constraint";
+    case FFSAT_E_BAD_KIND: return "unknown constraint kind";
+    case FFSAT_E_DEVICE_MISMATCH: return "device mismatch";
+    case FFSAT_E_NOMEM: return "out of memory";
+    case FFSAT_E_HIP: return "HIP runtime error";
+    case FFSAT_E_NONFINITE: return "non-finite input";
+    case FFSAT_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *ffsat_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *ffsat_version(void) { return "ffsat 0.1.0 (gfx950)"; }
+
+// ------------------------------------------------------------------ coefficients
+
+namespace {
+
+constexpr long double PI_L = 3.141592653589793238462643383279502884L;
+
+double truth(int kind, int param, int c)
+{
+    switch (kind) {
+    case FFSAT_KIND_OR: return c >= 1 ? -1.0 : 1.0;
+    case FFSAT_KIND_XOR: return (c % 2) == (param & 1) ? -1.0 : 1.0;
+    default: return c >= param ? -1.0 : 1.0;
+    }
+}
+
+using cld = std::complex<long double>;
+
+// All conjugated coefficients h_a = (1/N) sum_c f(c) exp(-2 pi i a c / N),
+// a = 0..floor(N/2), N = k + 1.  f is a step function of the count c, so
+// with its jumps d_j = f(j) - f(j-1) (j = 1..k) and z = exp(-2 pi i a / N),
+// z != 1, the sum over all N roots vanishes and
+//     h_a = (1/N) sum_j d_j (z^j - 1) / (1 - z),
+// one term per jump (OR and at-least-t have a single jump).  Angles are
+// reduced exactly in integers; arithmetic in long double.
+std::vector<cld> conj_coeffs(int kind, int param, int k)
+{
+    const long long N = k + 1;
+    std::vector<double> fv((size_t)k + 1);
+    for (int c = 0; c <= k; ++c) fv[(size_t)c] = truth(kind, param, c);
+    std::vector<std::pair<int, double>> jumps;
+    for (int j = 1; j <= k; ++j)
+        if (fv[(size_t)j] != fv[(size_t)j - 1]) jumps.emplace_back(j, fv[(size_t)j] - fv[(size_t)j - 1]);
+    auto root = [&](long long e) {   // exp(-2 pi i e / N)
+        const long long r = ((e % N) + N) % N;
+        const long double ang = -2.0L * PI_L * (long double)r / (long double)N;
+        return cld(cosl(ang), sinl(ang));
+    };
+    std::vector<cld> h((size_t)(N / 2) + 1);
+    long double s0 = 0;
+    for (int c = 0; c <= k; ++c) s0 += fv[(size_t)c];
+    h[0] = cld(s0 / N, 0.0L);
+    for (long long a = 1; a <= N / 2; ++a) {
+        const cld z = root(a);
+        const cld den = 1.0L - z;
+        cld acc = 0.0L;
+        for (const auto &jd : jumps) acc += (long double)jd.second * (root(a * jd.first) - 1.0L);
+        h[(size_t)a] = acc / den / (long double)N;
+    }
+    return h;
+}
+
+struct FreqD {
+    double tk, init, c0re, c0im, c1re, c1im;
+};
+
+struct TypeD {
+    int cls = CLASS_REAL;
+    double cst = 0, alpha = 0, beta = 0, c0r = 0, c1r = 0, pad = 1;
+    int has_real = 0;
+    int n1 = 0, n2 = 0;
+    std::vector<FreqD> fr;
+};
+
+// Transform-free product chains (App. B and its footnote for OR).
+TypeD real_or() { TypeD t; t.has_real = 1; t.alpha = 0.5; t.beta = 0.5; t.c0r = 2; t.c1r = 1; t.cst = -1; t.pad = 1; return t; }
+TypeD real_and() { TypeD t; t.has_real = 1; t.alpha = 0.5; t.beta = -0.5; t.c0r = -2; t.c1r = 1; t.cst = 1; t.pad = -1; return t; }
+TypeD real_xor(int p) { TypeD t; t.has_real = 1; t.alpha = 0; t.beta = 1; t.c0r = t.c1r = (p & 1) ? 1.0 : -1.0; t.cst = 0; t.pad = 1; return t; }
+TypeD real_const(double v) { TypeD t; t.cst = v; t.pad = 1; return t; }
+
+// Root-of-unity evaluation of a symmetric constraint (Alg. 2), with the
+// factor of literal i at frequency a taken in the bounded basis
+//   q_i + p_i z = (1+z)/2 + l_i (1-z)/2,  z = exp(2 pi i a / N)
+//              = e^{i th/2} (C - i S l_i),  th = 2 pi a / N,
+// rescaled to psi = 1 - i (S/C) l (form 1, C >= S) or (C/S) - i l (form 2);
+// the removed factor e^{i k th/2} C^k (or S^k), the padding literals of the
+// segment layout (value +1, count-neutral) and the power-of-two start value
+// of every segment are folded into c0 / c1 here, in long double.
+TypeD dft_type(const std::vector<cld> &hv, int k, int L)
+{
+    TypeD t;
+    t.cls = CLASS_DFT;
+    const int N = k + 1;
+    const int s = (k + L - 1) / L;
+    const int npad = L * s - k;
+    t.cst = (double)hv[0].real();
+    t.pad = 1.0;
+    std::vector<FreqD> f1, f2;
+    for (int a = 1; a <= k / 2; ++a) {
+        const cld h = hv[(size_t)a];
+        if (std::abs(h) < 1e-15L) continue;
+        const long double half = PI_L * a / N;
+        const long double C = cosl(half), S = sinl(half);
+        const bool form1 = C >= S;
+        const long double tk = form1 ? S / C : C / S;
+        const long double base = form1 ? C : S;
+        const long double mag2 = 1.0L + tk * tk;
+        const int e = (int)floorl((long double)s * log2l(mag2) / 4.0L);
+        const long long r2 = ((long long)a * k) % (2LL * N);   // phase k*th/2 = pi a k / N
+        const long double ph = PI_L * (long double)r2 / (long double)N;
+        const cld sigma = cld(cosl(ph), sinl(ph)) * powl(base, (long double)k);
+        const cld psipad = form1 ? cld(1.0L, -tk) : cld(tk, -1.0L);
+        cld corr = 1.0L;
+        for (int q = 0; q < npad; ++q) corr /= psipad;
+        const cld c0 = 2.0L * h * sigma * corr * ldexpl(1.0L, L * e);
+        const cld c1 = c0 * (form1 ? cld(0.0L, -tk) : cld(0.0L, -1.0L));
+        FreqD fd{(double)tk, (double)ldexpl(1.0L, -e), (double)c0.real(), (double)c0.imag(),
+                 (double)c1.real(), (double)c1.imag()};
+        (form1 ? f1 : f2).push_back(fd);
+    }
+    t.n1 = (int)f1.size();
+    t.n2 = (int)f2.size();
+    t.fr = f1;
+    t.fr.insert(t.fr.end(), f2.begin(), f2.end());
+    if (k % 2 == 1) {
+        // z = -1 (N even): the factor is l_i itself, a real product chain
+        const long double hn = hv[(size_t)N / 2].real();
+        if (fabsl(hn) >= 1e-15L) {
+            t.has_real = 1;
+            t.alpha = 0;
+            t.beta = 1;
+            t.c0r = t.c1r = (double)hn;
+        }
+    }
+    return t;
+}
+
+void shape_for(int ct, int k, int &seg, int &L)
+{
+    if (ct == CT_F32) seg = k <= 8 ? 8 : (k <= 16 ? 16 : 32);
+    else seg = k <= 8 ? 8 : 16;
+    const int need = (k + seg - 1) / seg;
+    L = 1;
+    while (L < need) L <<= 1;
+}
+
+struct TypeKey {
+    int cls, ct, kind, param, k, L;
+    bool operator<(const TypeKey &o) const
+    {
+        return std::tie(cls, ct, kind, param, k, L) < std::tie(o.cls, o.ct, o.kind, o.param, o.k, o.L);
+    }
+};
+
+enum { RK_OR = 100, RK_XOR = 101, RK_AND = 102, RK_CONST = 103 };
+
+template <typename T>
+ffsat_status upload(T **dst, const std::vector<T> &src, int64_t &bytes)
+{
+    *dst = nullptr;
+    if (src.empty()) return FFSAT_OK;
+    HIPCHK(hipMalloc((void **)dst, src.size() * sizeof(T)));
+    HIPCHK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    bytes += (int64_t)(src.size() * sizeof(T));
+    return FFSAT_OK;
+}
+
+}  // namespace
+
+extern "C" ffsat_status ffsat_coefficients(int32_t kind, int32_t k, int32_t param, double *h_out)
+{
+    if (!h_out || k < 1 || k > FFSAT_MAX_CONSTRAINT_LEN)
+        return fail(FFSAT_E_INVALID_ARG, "ffsat_coefficients: bad argument");
+    if (kind < 0 || kind > 2) return fail(FFSAT_E_BAD_KIND, "ffsat_coefficients: bad kind %d", kind);
+    const std::vector<cld> h = conj_coeffs(kind, param, k);
+    for (int a = 0; a <= (k + 1) / 2; ++a) {
+        h_out[2 * a] = (double)h[(size_t)a].real();
+        h_out[2 * a + 1] = (double)h[(size_t)a].imag();
+    }
+    return FFSAT_OK;
+}
+
+// ------------------------------------------------------------------ problem
+
+static ffsat_status validate(const ffsat_problem_desc *d)
+{
+    if (!d) return fail(FFSAT_E_INVALID_ARG, "problem description is NULL");
+    if (d->n_vars < 1) return fail(FFSAT_E_INVALID_ARG, "n_vars must be >= 1 (got %d)", d->n_vars);
+    if (d->n_cons < 1) return fail(FFSAT_E_INVALID_ARG, "n_cons must be >= 1 (got %d)", d->n_cons);
+    if (!d->con_ptr || !d->lits || !d->kinds || !d->params)
+        return fail(FFSAT_E_INVALID_ARG, "con_ptr, lits, kinds and params are required");
+    if (d->con_ptr[0] != 0) return fail(FFSAT_E_INVALID_ARG, "con_ptr[0] must be 0");
+    const int m = d->n_cons, n = d->n_vars;
+    for (int c = 0; c < m; ++c) {
+        const int64_t a = d->con_ptr[c], b = d->con_ptr[c + 1];
+        if (b < a) return fail(FFSAT_E_INVALID_ARG, "con_ptr decreases at constraint %d", c);
+        if (b == a) return fail(FFSAT_E_EMPTY_CONSTRAINT, "constraint %d has no literal", c);
+        if (b - a > FFSAT_MAX_CONSTRAINT_LEN)
+            return fail(FFSAT_E_UNSUPPORTED, "constraint %d has %lld literals (max %d)", c,
+                        (long long)(b - a), FFSAT_MAX_CONSTRAINT_LEN);
+        const int kd = d->kinds[c];
+        if (kd != FFSAT_KIND_OR && kd != FFSAT_KIND_XOR && kd != FFSAT_KIND_CARD_GE)
+            return fail(FFSAT_E_BAD_KIND, "constraint %d has kind %d", c, kd);
+    }
+    if (d->con_ptr[m] > (int64_t)INT32_MAX - 1)
+        return fail(FFSAT_E_UNSUPPORTED, "more than 2^31-1 literals");
+    std::vector<int32_t> stamp((size_t)n, -1);
+    for (int c = 0; c < m; ++c) {
+        for (int64_t i = d->con_ptr[c]; i < d->con_ptr[c + 1]; ++i) {
+            const int32_t l = d->lits[i];
+            if (l == 0 || l > n || l < -n)
+                return fail(FFSAT_E_VAR_RANGE, "literal %d of constraint %d is out of range", l, c);
+            const int v = (l > 0 ? l : -l) - 1;
+            if (stamp[v] == c)
+                return fail(FFSAT_E_DUP_VAR, "variable %d appears twice in constraint %d", v + 1, c);
+            stamp[v] = c;
+        }
+    }
+    if (d->weights) {
+        for (int c = 0; c < m; ++c)
+            if (!std::isfinite(d->weights[c]))
+                return fail(FFSAT_E_INVALID_ARG, "weight %d is not finite", c);
+    }
+    if (d->fp64_min_len < 0) return fail(FFSAT_E_INVALID_ARG, "fp64_min_len must be >= 0");
+    return FFSAT_OK;
+}
+
+static void free_layout(Layout &L)
+{
+    (void)hipFree(L.d_con);
+    (void)hipFree(L.d_lit);
+    (void)hipFree(L.d_vptr);
+    (void)hipFree(L.d_vslot);
+    (void)hipFree(L.d_pos);
+    (void)hipFree(L.d_t32);
+    (void)hipFree(L.d_t64);
+    (void)hipFree(L.d_f32);
+    (void)hipFree(L.d_f64);
+    L = Layout();
+}
+
+using CoeffMemo = std::map<std::tuple<int, int, int>, std::vector<cld>>;
+
+static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, int io, CoeffMemo &memo)
+{
+    Layout &Ly = p->lay[io];
+    Ly.io = io;
+    const int m = p->m, n = p->n;
+    const bool force_dft = (p->flags & FFSAT_FLAG_FORCE_DFT) != 0;
+
+    // 1. classify every constraint into a (type, bin)
+    std::map<TypeKey, int> type_index;
+    std::vector<TypeD> types;
+    struct Item { int c, k, type, bin; double cost; };
+    std::vector<Item> items((size_t)m);
+    struct BinKey {
+        int cls, ct, seg, L;
+        bool operator<(const BinKey &o) const { return std::tie(cls, ct, seg, L) < std::tie(o.cls, o.ct, o.seg, o.L); }
+    };
+    std::map<BinKey, int> bin_index;
+    std::vector<Bin> bins;
+    for (int c = 0; c < m; ++c) {
+        const int k = (int)(d->con_ptr[c + 1] - d->con_ptr[c]);
+        const int kind = d->kinds[c];
+        const int prm = d->params[c];
+        int cls, rk = -1, rparam = 0;
+        if (kind == FFSAT_KIND_CARD_GE && prm <= 0) { cls = CLASS_REAL; rk = RK_CONST; rparam = -1; }
+        else if (kind == FFSAT_KIND_CARD_GE && prm > k) { cls = CLASS_REAL; rk = RK_CONST; rparam = 1; }
+        else if (!force_dft && (kind == FFSAT_KIND_OR || (kind == FFSAT_KIND_CARD_GE && prm == 1))) { cls = CLASS_REAL; rk = RK_OR; }
+        else if (!force_dft && kind == FFSAT_KIND_XOR) { cls = CLASS_REAL; rk = RK_XOR; rparam = prm & 1; }
+        else if (!force_dft && kind == FFSAT_KIND_CARD_GE && prm == k) { cls = CLASS_REAL; rk = RK_AND; }
+        else cls = CLASS_DFT;
+        int ct;
+        if (io == IO_F64) ct = CT_F64;
+        else ct = (cls == CLASS_DFT && k >= p->fp64_min_len) ? CT_F64 : CT_F32;
+        int seg, L;
+        shape_for(ct, k, seg, L);
+        if (!eval_variant_exists(io, ct, cls, seg, L))
+            return fail(FFSAT_E_UNSUPPORTED, "no kernel variant for constraint %d (k=%d)", c, k);
+        TypeKey tk;
+        if (cls == CLASS_REAL) tk = TypeKey{cls, ct, rk, rparam, 0, 0};
+        else {
+            int nprm = kind == FFSAT_KIND_XOR ? (prm & 1) : (kind == FFSAT_KIND_OR ? 0 : prm);
+            tk = TypeKey{cls, ct, kind, nprm, k, L};
+        }
+        auto it = type_index.find(tk);
+        int ti;
+        if (it == type_index.end()) {
+            TypeD td;
+            if (cls == CLASS_DFT) {
+                auto key = std::make_tuple(tk.kind, tk.param, k);
+                auto mh = memo.find(key);
+                if (mh == memo.end()) mh = memo.emplace(key, conj_coeffs(tk.kind, tk.param, k)).first;
+                td = dft_type(mh->second, k, L);
+            }
+            else if (rk == RK_OR) td = real_or();
+            else if (rk == RK_XOR) td = real_xor(rparam);
+            else if (rk == RK_AND) td = real_and();
+            else td = real_const((double)rparam);
+            ti = (int)types.size();
+            types.push_back(td);
+            type_index[tk] = ti;
+        } else {
+            ti = it->second;
+        }
+        BinKey bk{cls, ct, seg, L};
+        auto bi = bin_index.find(bk);
+        int bidx;
+        if (bi == bin_index.end()) {
+            Bin b;
+            b.cls = cls; b.ct = ct; b.seg = seg; b.L = L;
+            bidx = (int)bins.size();
+            bins.push_back(b);
+            bin_index[bk] = bidx;
+        } else {
+            bidx = bi->second;
+        }
+        const double cost = cls == CLASS_DFT ? (double)k * (double)(types[ti].n1 + types[ti].n2 + 1) * 9.0
+                                             : (double)k * 4.0;
+        items[(size_t)c] = Item{c, k, ti, bidx, cost};
+        Bin &b = bins[(size_t)bidx];
+        // Algorithmic work per restart.  Per (literal, complex frequency):
+        // factor and running product 5 FLOPs, reverse product 5, leave-one-out
+        // dot 4; per frequency the step-iii dot 4.  Real chains: 8 FLOPs per
+        // literal.  Bytes: one gathered value and one slot per literal.
+        {
+            const TypeD &td = types[(size_t)ti];
+            const double nfc = (double)(td.n1 + td.n2);
+            b.flops += 14.0 * k * nfc + 4.0 * nfc + (td.has_real ? 8.0 * k : 0.0);
+            b.bytes += (io == IO_F32 ? 8.0 : 16.0) * k;
+        }
+        b.count += 1;
+        b.maxk = std::max(b.maxk, k);
+        b.cost += cost;
+        b.lits += k;
+    }
+
+    // 2. order bins by total cost (heaviest first), constraints by cost inside a bin
+    std::vector<int> border(bins.size());
+    for (size_t i = 0; i < bins.size(); ++i) border[i] = (int)i;
+    std::stable_sort(border.begin(), border.end(), [&](int a, int b) { return bins[a].cost > bins[b].cost; });
+    std::vector<int> rank(bins.size());
+    for (size_t r = 0; r < border.size(); ++r) rank[(size_t)border[r]] = (int)r;
+    std::stable_sort(items.begin(), items.end(), [&](const Item &a, const Item &b) {
+        if (rank[a.bin] != rank[b.bin]) return rank[a.bin] < rank[b.bin];
+        return a.cost > b.cost;
+    });
+    std::vector<Bin> sorted;
+    int first = 0;
+    for (int r : border) {
+        Bin b = bins[(size_t)r];
+        b.first = first;
+        first += b.count;
+        if (b.cls == CLASS_REAL) b.cpw = b.maxk <= 8 ? 16 : (b.maxk <= 32 ? 8 : 2);
+        else b.cpw = 1;
+        b.wpb = 4;
+        sorted.push_back(b);
+    }
+    Ly.bins = sorted;
+
+    // 3. binned descriptors and literals, original -> binned positions
+    std::vector<ConDesc> con((size_t)m);
+    std::vector<int32_t> lit((size_t)p->nnz);
+    std::vector<int32_t> pos((size_t)m);
+    int64_t off = 0;
+    for (int q = 0; q < m; ++q) {
+        const Item &it = items[(size_t)q];
+        con[(size_t)q] = ConDesc{(int32_t)off, it.k, it.type, it.c};
+        pos[(size_t)it.c] = q;
+        for (int i = 0; i < it.k; ++i) {
+            const int32_t l = d->lits[d->con_ptr[it.c] + i];
+            const int32_t v = (l > 0 ? l : -l) - 1;
+            lit[(size_t)(off + i)] = v | (l < 0 ? (int32_t)0x80000000u : 0);
+        }
+        off += it.k;
+    }
+    // 4. variable-major transpose over binned slots (ascending slot per variable)
+    std::vector<int32_t> vptr((size_t)n + 1, 0), vslot((size_t)p->nnz);
+    for (int64_t s = 0; s < p->nnz; ++s) vptr[(size_t)(lit[(size_t)s] & 0x7fffffff) + 1]++;
+    for (int v = 0; v < n; ++v) vptr[(size_t)v + 1] += vptr[(size_t)v];
+    {
+        std::vector<int32_t> fill(vptr.begin(), vptr.end() - 1);
+        for (int64_t s = 0; s < p->nnz; ++s) vslot[(size_t)fill[(size_t)(lit[(size_t)s] & 0x7fffffff)]++] = (int32_t)s;
+    }
+    // 5. type and frequency tables in both precisions
+    std::vector<TypeF32> t32;
+    std::vector<TypeF64> t64;
+    std::vector<FreqF32> f32;
+    std::vector<FreqF64> f64;
+    for (const TypeD &td : types) {
+        const int tab = (int)f64.size();
+        TypeF32 a{(float)td.cst, (float)td.alpha, (float)td.beta, (float)td.c0r, (float)td.c1r,
+                  (float)td.pad, td.n1, td.n2, td.has_real, tab};
+        TypeF64 b{td.cst, td.alpha, td.beta, td.c0r, td.c1r, td.pad, td.n1, td.n2, td.has_real, tab};
+        t32.push_back(a);
+        t64.push_back(b);
+        for (const FreqD &f : td.fr) {
+            f32.push_back(FreqF32{(float)f.tk, (float)f.init, (float)f.c0re, (float)f.c0im,
+                                  (float)f.c1re, (float)f.c1im, 0.f, 0.f});
+            f64.push_back(FreqF64{f.tk, f.init, f.c0re, f.c0im, f.c1re, f.c1im, 0.0, 0.0});
+        }
+    }
+    if (f32.empty()) {
+        f32.push_back(FreqF32{});
+        f64.push_back(FreqF64{});
+    }
+    Ly.n_types = (int)types.size();
+    Ly.n_freqs = (int64_t)f64.size();
+    ffsat_status st;
+    if ((st = upload(&Ly.d_con, con, p->device_bytes)) != FFSAT_OK) return st;
+    if ((st = upload(&Ly.d_lit, lit, p->device_bytes)) != FFSAT_OK) return st;
+    if ((st = upload(&Ly.d_vptr, vptr, p->device_bytes)) != FFSAT_OK) return st;
+    if ((st = upload(&Ly.d_vslot, vslot, p->device_bytes)) != FFSAT_OK) return st;
+    if ((st = upload(&Ly.d_pos, pos, p->device_bytes)) != FFSAT_OK) return st;
+    if ((st = upload(&Ly.d_t32, t32, p->device_bytes)) != FFSAT_OK) return st;
+    if ((st = upload(&Ly.d_t64, t64, p->device_bytes)) != FFSAT_OK) return st;
+    if ((st = upload(&Ly.d_f32, f32, p->device_bytes)) != FFSAT_OK) return st;
+    if ((st = upload(&Ly.d_f64, f64, p->device_bytes)) != FFSAT_OK) return st;
+    return FFSAT_OK;
+}
+
+static void free_problem(ffsat_problem *p)
+{
+    if (!p) return;
+    free_layout(p->lay[0]);
+    free_layout(p->lay[1]);
+    (void)hipFree(p->d_w);
+    (void)hipFree(p->d_kind);
+    (void)hipFree(p->d_param);
+    delete p;
+}
+
+extern "C" ffsat_status ffsat_problem_create(const ffsat_problem_desc *d, ffsat_problem **out)
+{
+    if (!out) return fail(FFSAT_E_INVALID_ARG, "out is NULL");
+    ffsat_status st = validate(d);
+    if (st != FFSAT_OK) return st;
+    int ndev = 0, cur = -1;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (d->device < 0 || d->device >= ndev)
+        return fail(FFSAT_E_DEVICE_MISMATCH, "device %d not present (%d devices)", d->device, ndev);
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != d->device)
+        return fail(FFSAT_E_DEVICE_MISMATCH, "device %d is not the current device (%d)", d->device, cur);
+    ffsat_problem *p = new ffsat_problem();
+    p->n = d->n_vars;
+    p->m = d->n_cons;
+    p->nnz = d->con_ptr[d->n_cons];
+    p->device = d->device;
+    p->fp64_min_len = d->fp64_min_len > 0 ? d->fp64_min_len : 257;
+    p->flags = d->flags;
+    for (int c = 0; c < p->m; ++c)
+        p->maxk = std::max(p->maxk, (int32_t)(d->con_ptr[c + 1] - d->con_ptr[c]));
+    std::vector<float> w((size_t)p->m, 1.0f);
+    if (d->weights) std::copy(d->weights, d->weights + p->m, w.begin());
+    std::vector<int32_t> kinds(d->kinds, d->kinds + p->m), params(d->params, d->params + p->m);
+    CoeffMemo memo;
+    if ((st = upload(&p->d_w, w, p->device_bytes)) != FFSAT_OK ||
+        (st = upload(&p->d_kind, kinds, p->device_bytes)) != FFSAT_OK ||
+        (st = upload(&p->d_param, params, p->device_bytes)) != FFSAT_OK ||
+        (st = build_layout(p, d, IO_F32, memo)) != FFSAT_OK ||
+        (st = build_layout(p, d, IO_F64, memo)) != FFSAT_OK) {
+        free_problem(p);
+        return st;
+    }
+    *out = p;
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_problem_destroy(ffsat_problem *p)
+{
+    free_problem(p);
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_problem_info_get(const ffsat_problem *p, ffsat_problem_info *info)
+{
+    if (!p || !info) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    info->n_vars = p->n;
+    info->n_cons = p->m;
+    info->nnz = p->nnz;
+    info->max_len = p->maxk;
+    info->n_bins_f32 = (int32_t)p->lay[0].bins.size();
+    info->n_bins_f64 = (int32_t)p->lay[1].bins.size();
+    info->device = p->device;
+    info->device_bytes = p->device_bytes;
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_set_weights(ffsat_problem *p, const float *w, int32_t on_device, void *stream)
+{
+    if (!p || !w) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    HIPCHK(hipMemcpyAsync(p->d_w, w, sizeof(float) * (size_t)p->m,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, (hipStream_t)stream));
+    if (!on_device) HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_get_weights(const ffsat_problem *p, float *w, int32_t on_device, void *stream)
+{
+    if (!p || !w) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    HIPCHK(hipMemcpyAsync(w, p->d_w, sizeof(float) * (size_t)p->m,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, (hipStream_t)stream));
+    if (!on_device) HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    return FFSAT_OK;
+}
+
+// ------------------------------------------------------------------ plan
+
+namespace ffsat {
+int fpart_rows_of(const std::vector<Bin> &bins)
+{
+    int rows = 0;
+    for (const Bin &b : bins) rows += (b.count + b.cpw - 1) / b.cpw;
+    return rows;
+}
+}  // namespace ffsat
+
+static ffsat_status ensure_workspace(ffsat_plan *pl, int io)
+{
+    if (pl->d_slot[io]) return FFSAT_OK;
+    const size_t es = io == IO_F32 ? sizeof(float) : sizeof(double);
+    const size_t B = (size_t)pl->B;
+    const size_t slot = (size_t)pl->p->nnz * B * es;
+    const size_t fpart = (size_t)pl->p->m * B * es;
+    const size_t ftmp = (size_t)f_splits(pl->p->m) * B * es;
+    HIPCHK(hipMalloc(&pl->d_slot[io], slot));
+    HIPCHK(hipMalloc(&pl->d_fpart[io], fpart));
+    HIPCHK(hipMalloc(&pl->d_ftmp[io], ftmp));
+    pl->device_bytes += (int64_t)(slot + fpart + ftmp);
+    return FFSAT_OK;
+}
+
+static std::string bin_key(const ffsat_plan *pl, const Bin &b, int io)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "gfx950|io%d|B%d|c%d|t%d|s%d|L%d|n%d|l%lld|k%d", io, pl->B, b.cls, b.ct, b.seg,
+             b.L, b.count, (long long)b.lits, b.maxk);
+    return buf;
+}
+
+static std::map<std::string, std::pair<int, int>> read_cache(const std::string &path)
+{
+    std::map<std::string, std::pair<int, int>> out;
+    std::ifstream f(path);
+    if (!f) return out;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    // entries: "key": [cpw, wpb]
+    size_t i = 0;
+    while ((i = s.find('"', i)) != std::string::npos) {
+        const size_t j = s.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = s.substr(i + 1, j - i - 1);
+        const size_t lb = s.find('[', j), rb = s.find(']', j);
+        if (lb == std::string::npos || rb == std::string::npos) break;
+        int cpw = 0, wpb = 0;
+        if (sscanf(s.c_str() + lb + 1, "%d , %d", &cpw, &wpb) == 2 && cpw > 0 && wpb > 0) out[key] = {cpw, wpb};
+        i = rb + 1;
+    }
+    return out;
+}
+
+static void write_cache(const std::string &path, const std::map<std::string, std::pair<int, int>> &m)
+{
+    std::ofstream f(path);
+    if (!f) return;
+    f << "{\n";
+    size_t q = 0;
+    for (const auto &kv : m) {
+        f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
+          << (++q < m.size() ? ",\n" : "\n");
+    }
+    f << "}\n";
+}
+
+template <typename IO>
+static EvalArgs<IO> base_args(ffsat_plan *pl, int io, const IO *x, IO *con_val, bool want_grad)
+{
+    const ffsat_problem *p = pl->p;
+    const Layout &Ly = p->lay[io];
+    EvalArgs<IO> a{};
+    a.x = x;
+    a.slot = (IO *)pl->d_slot[io];
+    a.fpart = (IO *)pl->d_fpart[io];
+    a.con_val = con_val;
+    a.con = Ly.d_con;
+    a.lit = Ly.d_lit;
+    a.w = p->d_w;
+    a.B = pl->B;
+    a.want_grad = want_grad ? 1 : 0;
+    return a;
+}
+
+static hipEvent_t prof_event(ffsat_plan *pl)
+{
+    if (!pl->prof_pool.empty()) {
+        hipEvent_t e = pl->prof_pool.back();
+        pl->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static bool prof_active(ffsat_plan *pl, hipStream_t s)
+{
+    if (!pl->profiling) return false;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+    return cs == hipStreamCaptureStatusNone;
+}
+
+static void prof_begin(ffsat_plan *pl, hipStream_t s, bool on, ProfRec &r, int io, int bin)
+{
+    r = ProfRec{io, bin, nullptr, nullptr};
+    if (!on) return;
+    r.e0 = prof_event(pl);
+    r.e1 = prof_event(pl);
+    if (r.e0) (void)hipEventRecord(r.e0, s);
+}
+
+static void prof_end(ffsat_plan *pl, hipStream_t s, ProfRec &r)
+{
+    if (!r.e0 || !r.e1) return;
+    (void)hipEventRecord(r.e1, s);
+    pl->prof_pending.push_back(r);
+}
+
+template <typename IO>
+static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream_t s)
+{
+    const Layout &Ly = pl->p->lay[io];
+    const bool prof = prof_active(pl, s);
+    int row0 = 0;
+    int bi = 0;
+    for (const Bin &b : pl->bins[io]) {
+        a.first = b.first;
+        a.count = b.count;
+        a.cpw = b.cpw;
+        a.n_rb = (pl->B + (64 / b.L) - 1) / (64 / b.L);
+        a.fpart_row0 = row0;
+        a.types = b.ct == CT_F32 ? (const void *)Ly.d_t32 : (const void *)Ly.d_t64;
+        a.freqs = b.ct == CT_F32 ? (const void *)Ly.d_f32 : (const void *)Ly.d_f64;
+        hipError_t e;
+        ProfRec rec;
+        prof_begin(pl, s, prof, rec, io, bi);
+        if constexpr (sizeof(IO) == 4) e = launch_eval_bin_f32(b, a, s);
+        else e = launch_eval_bin_f64(b, a, s);
+        prof_end(pl, s, rec);
+        if (e != hipSuccess) return e;
+        row0 += (b.count + b.cpw - 1) / b.cpw;
+        ++bi;
+    }
+    return hipSuccess;
+}
+
+extern "C" ffsat_status ffsat_plan_tune(ffsat_plan *pl, void *stream)
+{
+    if (!pl) return fail(FFSAT_E_INVALID_ARG, "NULL plan");
+    hipStream_t s = (hipStream_t)stream;
+    ffsat_status st = ensure_workspace(pl, IO_F32);
+    if (st != FFSAT_OK) return st;
+    const ffsat_problem *p = pl->p;
+    if (!pl->d_scratch_x) {
+        HIPCHK(hipMalloc(&pl->d_scratch_x, sizeof(float) * (size_t)p->n * (size_t)pl->B));
+        pl->device_bytes += (int64_t)(sizeof(float) * (size_t)p->n * (size_t)pl->B);
+        HIPCHK(launch_scratch_points(pl->d_scratch_x, (int64_t)p->n * pl->B, 12345u, s));
+    }
+    std::map<std::string, std::pair<int, int>> cache;
+    if (!pl->tune_cache.empty()) cache = read_cache(pl->tune_cache);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    EvalArgs<float> a = base_args<float>(pl, IO_F32, pl->d_scratch_x, nullptr, true);
+    const Layout &Ly = p->lay[IO_F32];
+    bool dirty = false;
+    for (Bin &b : pl->bins[IO_F32]) {
+        const std::string key = bin_key(pl, b, IO_F32);
+        auto hit = cache.find(key);
+        if (hit != cache.end()) {
+            b.cpw = hit->second.first;
+            b.wpb = hit->second.second;
+            continue;
+        }
+        a.first = b.first;
+        a.count = b.count;
+        a.n_rb = (pl->B + (64 / b.L) - 1) / (64 / b.L);
+        a.fpart_row0 = 0;
+        a.types = b.ct == CT_F32 ? (const void *)Ly.d_t32 : (const void *)Ly.d_t64;
+        a.freqs = b.ct == CT_F32 ? (const void *)Ly.d_f32 : (const void *)Ly.d_f64;
+        float best = 1e30f;
+        int bc = b.cpw, bw = b.wpb;
+        const int cpws[] = {1, 2, 4, 8, 16, 32, 64};
+        const int wpbs[] = {1, 2, 4};
+        for (int cpw : cpws) {
+            if (cpw > 1 && cpw > b.count) break;
+            for (int wpb : wpbs) {
+                Bin t = b;
+                t.cpw = cpw;
+                t.wpb = wpb;
+                a.cpw = cpw;
+                HIPCHK(launch_eval_bin_f32(t, a, s));
+                HIPCHK(hipEventRecord(e0, s));
+                const int reps = 3;
+                for (int r = 0; r < reps; ++r) HIPCHK(launch_eval_bin_f32(t, a, s));
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                ms /= reps;
+                if (ms < best * 0.97f) { best = ms; bc = cpw; bw = wpb; }
+            }
+        }
+        b.cpw = bc;
+        b.wpb = bw;
+        cache[key] = {bc, bw};
+        dirty = true;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (dirty && !pl->tune_cache.empty()) write_cache(pl->tune_cache, cache);
+    pl->fpart_rows[IO_F32] = fpart_rows_of(pl->bins[IO_F32]);
+    // cached graphs baked the old shapes
+    for (auto &kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+    pl->graphs.clear();
+    pl->tuned = true;
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffsat_plan_opts *opts, ffsat_plan **out)
+{
+    if (!p || !out) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    if (B < 1) return fail(FFSAT_E_INVALID_ARG, "B must be >= 1 (got %d)", B);
+    if ((int64_t)B * (int64_t)std::max<int64_t>(p->nnz, p->m) > ((int64_t)1 << 40))
+        return fail(FFSAT_E_UNSUPPORTED, "nnz * B too large");
+    ffsat_plan *pl = new ffsat_plan();
+    pl->p = p;
+    pl->B = B;
+    pl->bins[0] = p->lay[0].bins;
+    pl->bins[1] = p->lay[1].bins;
+    pl->fpart_rows[0] = fpart_rows_of(pl->bins[0]);
+    pl->fpart_rows[1] = fpart_rows_of(pl->bins[1]);
+    pl->use_graphs = opts ? opts->use_graphs != 0 : true;
+    if (opts && opts->tune_cache) pl->tune_cache = opts->tune_cache;
+    ffsat_status st = ensure_workspace(pl, IO_F32);
+    if (st == FFSAT_OK) {
+        hipError_t e = hipMalloc(&pl->d_flag, sizeof(int32_t));
+        if (e != hipSuccess) st = fail(FFSAT_E_NOMEM, "hipMalloc flag: %s", hipGetErrorString(e));
+    }
+    if (st == FFSAT_OK && opts && opts->autotune) {
+        st = ffsat_plan_tune(pl, nullptr);
+        if (st == FFSAT_OK) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) st = fail(FFSAT_E_HIP, "sync after tuning: %s", hipGetErrorString(e));
+        }
+    }
+    if (st != FFSAT_OK) {
+        ffsat_plan_destroy(pl);
+        return st;
+    }
+    *out = pl;
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_plan_profile(ffsat_plan *pl, int32_t on)
+{
+    if (!pl) return fail(FFSAT_E_INVALID_ARG, "NULL plan");
+    pl->profiling = on != 0;
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_plan_profile_read(ffsat_plan *pl, int32_t reset, char *buf, size_t len)
+{
+    if (!pl || !buf || len == 0) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    for (ProfRec &r : pl->prof_pending) {
+        HIPCHK(hipEventSynchronize(r.e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.e0, r.e1));
+        auto &acc = pl->prof_acc[{r.io, r.bin}];
+        acc.first += ms;
+        acc.second += 1;
+        pl->prof_pool.push_back(r.e0);
+        pl->prof_pool.push_back(r.e1);
+    }
+    pl->prof_pending.clear();
+    std::ostringstream o;
+    o << "{\"kernels\": [";
+    size_t q = 0;
+    for (const auto &kv : pl->prof_acc) {
+        o << (q++ ? ", " : "") << "{\"io\": \"" << (kv.first.first ? "f64" : "f32") << "\", \"bin\": " << kv.first.second
+          << ", \"launches\": " << kv.second.second << ", \"total_ms\": " << kv.second.first
+          << ", \"avg_ms\": " << (kv.second.second ? kv.second.first / (double)kv.second.second : 0.0) << "}";
+    }
+    o << "]}";
+    if (reset) pl->prof_acc.clear();
+    const std::string str = o.str();
+    const size_t nb = std::min(len - 1, str.size());
+    memcpy(buf, str.data(), nb);
+    buf[nb] = 0;
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_plan_destroy(ffsat_plan *pl)
+{
+    if (!pl) return FFSAT_OK;
+    for (ProfRec &r : pl->prof_pending) {
+        (void)hipEventDestroy(r.e0);
+        (void)hipEventDestroy(r.e1);
+    }
+    for (hipEvent_t e : pl->prof_pool) (void)hipEventDestroy(e);
+    for (auto &kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (int io = 0; io < 2; ++io) {
+        (void)hipFree(pl->d_slot[io]);
+        (void)hipFree(pl->d_fpart[io]);
+        (void)hipFree(pl->d_ftmp[io]);
+    }
+    (void)hipFree(pl->d_flag);
+    (void)hipFree(pl->d_scratch_x);
+    if (pl->cap) (void)hipStreamDestroy(pl->cap);
+    delete pl;
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, size_t len)
+{
+    if (!pl || !buf || len == 0) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    std::ostringstream o;
+    o << "{\"B\": " << pl->B << ", \"tuned\": " << (pl->tuned ? "true" : "false") << ", \"bins\": {";
+    for (int io = 0; io < 2; ++io) {
+        o << (io ? ", " : "") << "\"" << (io ? "f64" : "f32") << "\": [";
+        for (size_t i = 0; i < pl->bins[io].size(); ++i) {
+            const Bin &b = pl->bins[io][i];
+            o << (i ? ", " : "") << "{\"class\": \"" << (b.cls == CLASS_DFT ? "dft" : "real") << "\", \"ct\": \""
+              << (b.ct == CT_F32 ? "f32" : "f64") << "\", \"seg\": " << b.seg << ", \"L\": " << b.L
+              << ", \"first\": " << b.first << ", \"count\": " << b.count << ", \"maxk\": " << b.maxk
+              << ", \"lits\": " << b.lits << ", \"cost\": " << b.cost << ", \"flops_per_restart\": " << b.flops
+              << ", \"bytes_per_restart\": " << b.bytes << ", \"cpw\": " << b.cpw
+              << ", \"wpb\": " << b.wpb << "}";
+        }
+        o << "]";
+    }
+    o << "}}";
+    const std::string s = o.str();
+    const size_t nb = std::min(len - 1, s.size());
+    memcpy(buf, s.data(), nb);
+    buf[nb] = 0;
+    return FFSAT_OK;
+}
+
+// ------------------------------------------------------------------ evaluation
+
+template <typename IO>
+static ffsat_status check_finite(ffsat_plan *pl, const IO *x, hipStream_t s)
+{
+    if (!(pl->p->flags & FFSAT_FLAG_DEBUG_CHECKS)) return FFSAT_OK;
+    HIPCHK(launch_fill_i32(pl->d_flag, 1, 0, s));
+    const int64_t tot = (int64_t)pl->p->n * pl->B;
+    if constexpr (sizeof(IO) == 4) HIPCHK(launch_nonfinite_f32(tot, (const float *)x, pl->d_flag, s));
+    else HIPCHK(launch_nonfinite_f64(tot, (const double *)x, pl->d_flag, s));
+    int32_t h = 0;
+    HIPCHK(hipMemcpyAsync(&h, pl->d_flag, sizeof h, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h) return fail(FFSAT_E_NONFINITE, "input point contains NaN or Inf");
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_eval(ffsat_plan *pl, const float *x, float *F, float *grad, float *con_val, void *stream)
+{
+    if (!pl || !x) return fail(FFSAT_E_INVALID_ARG, "NULL plan or x");
+    hipStream_t s = (hipStream_t)stream;
+    ffsat_status st = ensure_workspace(pl, IO_F32);
+    if (st != FFSAT_OK) return st;
+    if ((st = check_finite<float>(pl, x, s)) != FFSAT_OK) return st;
+    if (!F && !grad && !con_val) return FFSAT_OK;
+    EvalArgs<float> a = base_args<float>(pl, IO_F32, x, con_val, grad != nullptr);
+    HIPCHK(enqueue_bins<float>(pl, IO_F32, a, s));
+    const Layout &Ly = pl->p->lay[IO_F32];
+    ProfRec rec;
+    prof_begin(pl, s, prof_active(pl, s), rec, IO_F32, -1);
+    hipError_t e = launch_reduce_f32(pl->p->n, pl->B, Ly.d_vptr, Ly.d_vslot, (const float *)pl->d_slot[0], grad,
+                                     nullptr, 0.f, (const float *)pl->d_fpart[0], pl->fpart_rows[0],
+                                     (float *)pl->d_ftmp[0], F, s);
+    prof_end(pl, s, rec);
+    HIPCHK(e);
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_eval_f64(ffsat_plan *pl, const double *x, double *F, double *grad, double *con_val,
+                                       void *stream)
+{
+    if (!pl || !x) return fail(FFSAT_E_INVALID_ARG, "NULL plan or x");
+    hipStream_t s = (hipStream_t)stream;
+    ffsat_status st = ensure_workspace(pl, IO_F64);
+    if (st != FFSAT_OK) return st;
+    if ((st = check_finite<double>(pl, x, s)) != FFSAT_OK) return st;
+    if (!F && !grad && !con_val) return FFSAT_OK;
+    EvalArgs<double> a = base_args<double>(pl, IO_F64, x, con_val, grad != nullptr);
+    HIPCHK(enqueue_bins<double>(pl, IO_F64, a, s));
+    const Layout &Ly = pl->p->lay[IO_F64];
+    ProfRec rec;
+    prof_begin(pl, s, prof_active(pl, s), rec, IO_F64, -1);
+    hipError_t e = launch_reduce_f64(pl->p->n, pl->B, Ly.d_vptr, Ly.d_vslot, (const double *)pl->d_slot[1], grad,
+                                     (const double *)pl->d_fpart[1], pl->fpart_rows[1], (double *)pl->d_ftmp[1], F, s);
+    prof_end(pl, s, rec);
+    HIPCHK(e);
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_step(ffsat_plan *pl, float *x, const float *grad, const float *eta_B, float eta,
+                                   void *stream)
+{
+    if (!pl || !x || !grad) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    HIPCHK(launch_step_f32((int64_t)pl->p->n * pl->B, pl->B, x, grad, eta_B, eta, (hipStream_t)stream));
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_step_f64(ffsat_plan *pl, double *x, const double *grad, const double *eta_B,
+                                       double eta, void *stream)
+{
+    if (!pl || !x || !grad) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    HIPCHK(launch_step_f64((int64_t)pl->p->n * pl->B, pl->B, x, grad, eta_B, eta, (hipStream_t)stream));
+    return FFSAT_OK;
+}
+
+static hipError_t enqueue_step_iter(ffsat_plan *pl, float *x, float eta, float *F, hipStream_t s)
+{
+    EvalArgs<float> a = base_args<float>(pl, IO_F32, x, nullptr, true);
+    hipError_t e = enqueue_bins<float>(pl, IO_F32, a, s);
+    if (e != hipSuccess) return e;
+    const Layout &Ly = pl->p->lay[IO_F32];
+    ProfRec rec;
+    prof_begin(pl, s, prof_active(pl, s), rec, IO_F32, -1);
+    e = launch_reduce_f32(pl->p->n, pl->B, Ly.d_vptr, Ly.d_vslot, (const float *)pl->d_slot[0], nullptr, x, eta,
+                          (const float *)pl->d_fpart[0], pl->fpart_rows[0], (float *)pl->d_ftmp[0], F, s);
+    prof_end(pl, s, rec);
+    return e;
+}
+
+extern "C" ffsat_status ffsat_run_steps(ffsat_plan *pl, float *x, int32_t T, float eta, float *F_last, void *stream)
+{
+    if (!pl || !x) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    if (T < 0) return fail(FFSAT_E_INVALID_ARG, "T must be >= 0");
+    if (T == 0) return FFSAT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    ffsat_status st = ensure_workspace(pl, IO_F32);
+    if (st != FFSAT_OK) return st;
+    if ((st = check_finite<float>(pl, x, s)) != FFSAT_OK) return st;
+    if (!pl->use_graphs) {
+        for (int t = 0; t < T; ++t) HIPCHK(enqueue_step_iter(pl, x, eta, t == T - 1 ? F_last : nullptr, s));
+        return FFSAT_OK;
+    }
+    const GraphKey key{x, T, eta, F_last};
+    auto it = pl->graphs.find(key);
+    if (it == pl->graphs.end()) {
+        if (!pl->cap) HIPCHK(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int t = 0; t < T && e == hipSuccess; ++t)
+            e = enqueue_step_iter(pl, x, eta, t == T - 1 ? F_last : nullptr, pl->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(pl->cap, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(FFSAT_E_HIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        hipGraphExec_t ex = nullptr;
+        hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) return fail(FFSAT_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e3));
+        if (pl->graphs.size() >= 16) {
+            for (auto &kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+            pl->graphs.clear();
+        }
+        it = pl->graphs.emplace(key, ex).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, s));
+    return FFSAT_OK;
+}
+
+// ------------------------------------------------------------------ check, weights
+
+extern "C" ffsat_status ffsat_round_check(ffsat_plan *pl, const float *x, uint32_t *assign_bits, int32_t *n_sat,
+                                          uint32_t *unsat_bits, int32_t *U, void *stream)
+{
+    if (!pl || !x) return fail(FFSAT_E_INVALID_ARG, "NULL plan or x");
+    HIPCHK(launch_check_f32(pl->p, pl->B, x, assign_bits, n_sat, unsat_bits, U, (hipStream_t)stream));
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_round_check_f64(ffsat_plan *pl, const double *x, uint32_t *assign_bits,
+                                              int32_t *n_sat, uint32_t *unsat_bits, int32_t *U, void *stream)
+{
+    if (!pl || !x) return fail(FFSAT_E_INVALID_ARG, "NULL plan or x");
+    HIPCHK(launch_check_f64(pl->p, pl->B, x, assign_bits, n_sat, unsat_bits, U, (hipStream_t)stream));
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_erwa_update(ffsat_plan *pl, const int32_t *U, float alpha, void *stream)
+{
+    if (!pl || !U) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    if (!(alpha >= 0.f && alpha <= 1.f)) return fail(FFSAT_E_INVALID_ARG, "alpha must be in [0, 1]");
+    HIPCHK(launch_erwa(pl->p->m, U, pl->p->d_w, alpha, (hipStream_t)stream));
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_weight_grad(ffsat_plan *pl, const float *con_val, const float *gF, float *gw,
+                                          void *stream)
+{
+    if (!pl || !con_val || !gF || !gw) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    HIPCHK(launch_wgrad(pl->p->m, pl->B, con_val, gF, gw, (hipStream_t)stream));
+    return FFSAT_OK;
+}

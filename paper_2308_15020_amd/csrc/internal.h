@@ -1,0 +1,187 @@
+// Internal types of the ffsat HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "ffsat.h"
+
+namespace ffsat {
+
+// Kernel classes: REAL = transform-free product chains (OR, XOR, AND,
+// constants; the Nyquist term of the root-of-unity path is the same chain);
+// DFT = root-of-unity frequencies (complex chains) + optional real chain.
+enum { CLASS_REAL = 0, CLASS_DFT = 1 };
+enum { CT_F32 = 0, CT_F64 = 1 };
+enum { IO_F32 = 0, IO_F64 = 1 };
+
+// Per distinct constraint type.  WE = cst + sum over complex frequencies of
+// Re(c0 * prod psi) + c0r * prod (alpha + beta l); gradients likewise with
+// c1 / c1r and leave-one-out products.
+template <typename T>
+struct TypeT {
+    T cst, alpha, beta, c0r, c1r, pad;
+    int32_t n1, n2, has_real, tab;
+};
+// One complex frequency.  Form 1 (first n1 entries of a type): factor
+// psi = 1 - i*tk*l.  Form 2 (next n2 entries): psi = tk - i*l.  Each lane
+// starts its segment product at `init` (an exact power of two that centres
+// the magnitude range); c0/c1 fold in the scaling.
+template <typename T>
+struct FreqT {
+    T tk, init, c0re, c0im, c1re, c1im, p0, p1;
+};
+using TypeF32 = TypeT<float>;
+using TypeF64 = TypeT<double>;
+using FreqF32 = FreqT<float>;
+using FreqF64 = FreqT<double>;
+
+struct ConDesc {
+    int32_t off;   // first literal slot (binned literal order)
+    int32_t k;     // length
+    int32_t type;  // index into the type tables
+    int32_t orig;  // original constraint index
+};
+
+struct Bin {
+    int cls = CLASS_REAL;
+    int ct = CT_F32;
+    int seg = 8, L = 1;
+    int first = 0, count = 0;   // constraint range in binned order
+    int maxk = 0;
+    double cost = 0;            // estimated VALU work per restart
+    int64_t lits = 0;           // literal slots in the bin
+    double flops = 0;           // algorithmic FLOPs per restart (value + gradient)
+    double bytes = 0;           // algorithmic HBM bytes per restart (gathers + slot writes)
+    int cpw = 1, wpb = 4;       // tile shape: constraints per wave, waves per block
+};
+
+struct ProfRec {
+    int io, bin;                // bin = -1: gradient / objective reduction
+    hipEvent_t e0, e1;
+};
+
+struct Layout {
+    int io = IO_F32;
+    std::vector<Bin> bins;
+    ConDesc *d_con = nullptr;
+    int32_t *d_lit = nullptr;    // var | (negated << 31), binned order
+    int32_t *d_vptr = nullptr;   // [n+1] variable -> slot CSR
+    int32_t *d_vslot = nullptr;  // [nnz]
+    int32_t *d_pos = nullptr;    // [m] original index -> binned position
+    TypeF32 *d_t32 = nullptr;
+    TypeF64 *d_t64 = nullptr;
+    FreqF32 *d_f32 = nullptr;
+    FreqF64 *d_f64 = nullptr;
+    int n_types = 0;
+    int64_t n_freqs = 0;
+};
+
+}  // namespace ffsat
+
+struct ffsat_problem {
+    int32_t n = 0, m = 0;
+    int64_t nnz = 0;
+    int32_t maxk = 0;
+    int32_t device = 0;
+    int32_t fp64_min_len = 257;
+    uint32_t flags = 0;
+    float *d_w = nullptr;        // weights, original order
+    int32_t *d_kind = nullptr;   // original order
+    int32_t *d_param = nullptr;
+    ffsat::Layout lay[2];
+    int64_t device_bytes = 0;
+};
+
+namespace ffsat {
+
+template <typename IO>
+struct EvalArgs {
+    const IO *x;
+    IO *slot;
+    IO *fpart;
+    IO *con_val;
+    const ConDesc *con;
+    const int32_t *lit;
+    const float *w;
+    const void *types;
+    const void *freqs;
+    int B, first, count, cpw, n_rb, fpart_row0, want_grad, pad_;
+};
+
+struct GraphKey {
+    const void *x;
+    int32_t T;
+    float eta;
+    const void *F;
+    bool operator<(const GraphKey &o) const {
+        if (x != o.x) return x < o.x;
+        if (T != o.T) return T < o.T;
+        if (eta != o.eta) return eta < o.eta;
+        return F < o.F;
+    }
+};
+
+}  // namespace ffsat
+
+struct ffsat_plan {
+    ffsat_problem *p = nullptr;
+    int32_t B = 0;
+    std::vector<ffsat::Bin> bins[2];   // tuned copies of the problem's bins
+    void *d_slot[2] = {nullptr, nullptr};
+    void *d_fpart[2] = {nullptr, nullptr};
+    void *d_ftmp[2] = {nullptr, nullptr};
+    int fpart_rows[2] = {0, 0};
+    int32_t *d_flag = nullptr;       // debug non-finite flag
+    float *d_scratch_x = nullptr;    // autotuner input
+    hipStream_t cap = nullptr;       // capture stream for graphs
+    bool use_graphs = true;
+    bool tuned = false;
+    std::string tune_cache;
+    std::map<ffsat::GraphKey, hipGraphExec_t> graphs;
+    int64_t device_bytes = 0;
+    bool profiling = false;
+    std::vector<ffsat::ProfRec> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    std::map<std::pair<int, int>, std::pair<double, int64_t>> prof_acc;   // (io, bin) -> (ms, launches)
+};
+
+namespace ffsat {
+
+// kernels (eval.hip / aux.hip)
+hipError_t launch_eval_bin_f32(const Bin &bin, const EvalArgs<float> &a, hipStream_t s);
+hipError_t launch_eval_bin_f64(const Bin &bin, const EvalArgs<double> &a, hipStream_t s);
+bool eval_variant_exists(int io, int ct, int cls, int seg, int L);
+
+hipError_t launch_reduce_f32(int n, int B, const int32_t *vptr, const int32_t *vslot,
+                             const float *slot, float *grad, float *x_step, float eta,
+                             const float *fpart, int rows, float *ftmp, float *F, hipStream_t s);
+hipError_t launch_reduce_f64(int n, int B, const int32_t *vptr, const int32_t *vslot,
+                             const double *slot, double *grad, const double *fpart, int rows,
+                             double *ftmp, double *F, hipStream_t s);
+hipError_t launch_step_f32(int64_t total, int B, float *x, const float *g, const float *eta_b,
+                           float eta, hipStream_t s);
+hipError_t launch_step_f64(int64_t total, int B, double *x, const double *g,
+                           const double *eta_b, double eta, hipStream_t s);
+hipError_t launch_check_f32(const ffsat_problem *p, int B, const float *x, uint32_t *assign_bits,
+                            int32_t *n_sat, uint32_t *unsat_bits, int32_t *U, hipStream_t s);
+hipError_t launch_check_f64(const ffsat_problem *p, int B, const double *x,
+                            uint32_t *assign_bits, int32_t *n_sat, uint32_t *unsat_bits,
+                            int32_t *U, hipStream_t s);
+hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, hipStream_t s);
+hipError_t launch_wgrad(int m, int B, const float *con_val, const float *gF, float *gw,
+                        hipStream_t s);
+hipError_t launch_nonfinite_f32(int64_t total, const float *x, int32_t *flag, hipStream_t s);
+hipError_t launch_nonfinite_f64(int64_t total, const double *x, int32_t *flag, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_scratch_points(float *x, int64_t total, uint32_t seed, hipStream_t s);
+
+// number of F-partial rows of a bin list
+int fpart_rows_of(const std::vector<Bin> &bins);
+int f_splits(int rows);
+
+}  // namespace ffsat

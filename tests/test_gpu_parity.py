@@ -1,0 +1,265 @@
+"""HIP path against the FP64 oracle (needs an MI355X).
+
+Every comparison uses the same seeded inputs on both sides; floating-point
+results are compared at the natural scale (per-constraint values to 1e-5
+absolute, the objective relative to sum |w|, the gradient of a variable
+relative to the weight of its constraints), integer results bit-exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_cases import TOL32, TOL64, errors, every_bin_instance, points, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ffs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_15020_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def mixed(ffs):
+    inst = every_bin_instance()
+    prob = ffs.Problem(inst, device=0)
+    return inst, prob
+
+
+def _gpu_eval(plan, x, dtype=torch.float32, con=True):
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(DEV, dtype)
+    out = plan.eval(xt, want_con=con)
+    torch.cuda.synchronize()
+    return to_np(out)
+
+
+def test_problem_bins_cover_all_variants(mixed):
+    inst, prob = mixed
+    info = prob.info()
+    assert info["n_cons"] == inst.m and info["nnz"] == inst.nnz and info["max_len"] == 512
+    assert info["n_bins_f32"] >= 12 and info["n_bins_f64"] >= 8
+
+
+@pytest.mark.parametrize("dist", ["uniform", "near_corner", "corner", "mixed_edge"])
+@pytest.mark.parametrize("B", [1, 70])
+def test_eval_f32_every_bin(ffs, mixed, dist, B):
+    inst, prob = mixed
+    plan = ffs.Plan(prob, B)
+    x = points(inst, B, 100 + B, dist)
+    g = _gpu_eval(plan, x)
+    ref = oracle.eval_batch(inst, x.astype(np.float64), want_con=True)
+    e = errors(inst, g, ref)
+    print(dist, B, e)
+    assert e["con_val"] <= TOL32 and e["F"] <= TOL32 and e["grad"] <= TOL32, e
+
+
+@pytest.mark.parametrize("dist", ["uniform", "near_corner", "mixed_edge"])
+def test_eval_f64_every_bin(ffs, mixed, dist):
+    inst, prob = mixed
+    B = 67
+    plan = ffs.Plan(prob, B)
+    x = points(inst, B, 7, dist).astype(np.float64)
+    g = _gpu_eval(plan, x, torch.float64)
+    ref = oracle.eval_batch(inst, x, want_con=True)
+    e = errors(inst, g, ref)
+    print(dist, e)
+    assert e["con_val"] <= TOL64 and e["F"] <= TOL64 and e["grad"] <= TOL64, e
+
+
+def test_force_dft_matches_closed_forms(ffs):
+    """OR and XOR through the root-of-unity path against the closed forms."""
+    inst = workloads.random_hybrid(600, 5, n_or=120, or_len=(1, 64), n_xor=120, xor_len=(1, 300),
+                                   n_card=10, card_len=(2, 40), weights="uniform")
+    prob = ffs.Problem(inst, device=0, flags=ffs.FLAG_FORCE_DFT)
+    B = 65
+    plan = ffs.Plan(prob, B)
+    for dist in ("uniform", "near_corner"):
+        x = points(inst, B, 3, dist)
+        g = _gpu_eval(plan, x)
+        ref = oracle.eval_batch(inst, x.astype(np.float64), want_con=True, route=oracle.ROUTE_AUTH)
+        e = errors(inst, g, ref)
+        print(dist, e)
+        assert e["con_val"] <= TOL32 and e["grad"] <= TOL32, e
+
+
+def test_fp64_threshold_option(ffs, mixed):
+    """fp64_min_len moves long root-of-unity products to FP64; values agree."""
+    inst, _ = mixed
+    prob = ffs.Problem(inst, device=0, fp64_min_len=20)
+    B = 64
+    plan = ffs.Plan(prob, B)
+    x = points(inst, B, 9, "uniform")
+    g = _gpu_eval(plan, x)
+    ref = oracle.eval_batch(inst, x.astype(np.float64), want_con=True)
+    e = errors(inst, g, ref)
+    assert e["con_val"] <= TOL32 and e["grad"] <= TOL32, e
+
+
+def test_step_bit_exact(ffs, mixed):
+    inst, prob = mixed
+    B = 77
+    plan = ffs.Plan(prob, B)
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-1.2, 1.2, (inst.n_vars, B)).astype(np.float32)
+    gr = rng.normal(size=(inst.n_vars, B)).astype(np.float32)
+    eb = rng.uniform(0, 0.5, B).astype(np.float32)
+    for eta, use_b in ((0.05, False), (0.3, True)):
+        xt = torch.from_numpy(x).to(DEV)
+        plan.step(xt, torch.from_numpy(gr).to(DEV), eta, torch.from_numpy(eb).to(DEV) if use_b else None)
+        want = oracle.step_f32(x, gr, eta, eb if use_b else None)
+        assert np.array_equal(xt.cpu().numpy(), want)
+    x64 = x.astype(np.float64)
+    xt = torch.from_numpy(x64).to(DEV)
+    plan.step(xt, torch.from_numpy(gr.astype(np.float64)).to(DEV), 0.1)
+    assert np.array_equal(xt.cpu().numpy(), oracle.step_f64(x64, gr.astype(np.float64), 0.1))
+
+
+@pytest.mark.parametrize("dist", ["uniform", "corner", "mixed_edge"])
+def test_round_check_bit_exact(ffs, mixed, dist):
+    inst, prob = mixed
+    B = 100
+    plan = ffs.Plan(prob, B)
+    x = points(inst, B, 12, dist)
+    for dt in (torch.float32, torch.float64):
+        xt = torch.from_numpy(x).to(DEV, dt)
+        out = to_np(plan.round_check(xt))
+        ref = oracle.check(inst, x.astype(np.float64))
+        assert np.array_equal(out["n_sat"], ref["n_sat"])
+        assert np.array_equal(out["U"], ref["U"])
+        assert np.array_equal(out["unsat_bits"].view(np.uint32), ref["unsat_bits"])
+        assert np.array_equal(out["assign_bits"].view(np.uint32), ref["assign_bits"])
+
+
+def test_weights_erwa_and_weight_gradient(ffs, mixed):
+    inst, prob = mixed
+    B = 96
+    plan = ffs.Plan(prob, B)
+    w0 = prob.get_weights().cpu().numpy()
+    assert np.array_equal(w0, inst.weights)
+    x = points(inst, B, 21, "uniform")
+    xt = torch.from_numpy(x).to(DEV)
+    U = plan.round_check(xt, want=("U",))["U"]
+    plan.erwa_update(U, 0.4)
+    w1 = prob.get_weights().cpu().numpy()
+    want = oracle.erwa(U.cpu().numpy(), w0.astype(np.float64), 0.4)
+    assert np.max(np.abs(w1 - want)) <= 1e-6
+    # zero counts: r = 0
+    plan.erwa_update(torch.zeros(inst.m, dtype=torch.int32, device=DEV), 0.4)
+    w2 = prob.get_weights().cpu().numpy()
+    assert np.max(np.abs(w2 - 0.6 * w1.astype(np.float64))) <= 1e-6
+    # the objective uses the updated weights
+    out = plan.eval(xt, want_con=True)
+    ref = oracle.eval_batch(inst, x.astype(np.float64), w=w2.astype(np.float64), want_con=True)
+    e = errors(inst, to_np(out), ref)
+    assert e["F"] <= TOL32 and e["grad"] <= TOL32
+    gF = torch.from_numpy(np.random.default_rng(2).normal(size=B).astype(np.float32)).to(DEV)
+    gw = plan.weight_grad(out["con_val"], gF).cpu().numpy()
+    want = oracle.wgrad(ref["con_val"], gF.cpu().numpy().astype(np.float64))
+    assert np.max(np.abs(gw - want)) <= TOL32 * np.abs(gF.cpu().numpy()).sum()
+    prob.set_weights(inst.weights)
+    assert np.array_equal(prob.get_weights().cpu().numpy(), inst.weights)
+
+
+def test_determinism(ffs, mixed):
+    inst, prob = mixed
+    B = 128
+    plan = ffs.Plan(prob, B)
+    x = torch.from_numpy(points(inst, B, 5, "uniform")).to(DEV)
+    a = to_np(plan.eval(x, want_con=True))
+    b = to_np(plan.eval(x, want_con=True))
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_run_steps_graph_equals_eager_loop(ffs, mixed):
+    inst, prob = mixed
+    B = 72
+    x0 = points(inst, B, 31, "uniform")
+    T, eta = 7, 0.05
+    res = []
+    for graphs in (True, False):
+        plan = ffs.Plan(prob, B, use_graphs=graphs)
+        x = torch.from_numpy(x0).to(DEV)
+        F = torch.empty(B, device=DEV)
+        plan.run_steps(x, T, eta, F)
+        plan.run_steps(x, T, eta, F)        # replay of the cached graph
+        res.append((x.cpu().numpy(), F.cpu().numpy()))
+    plan = ffs.Plan(prob, B)
+    x = torch.from_numpy(x0).to(DEV)
+    for t in range(2 * T):
+        out = plan.eval(x, want_F=(t == 2 * T - 1))
+        if t == 2 * T - 1:
+            Flast = out["F"].cpu().numpy()
+        plan.step(x, out["grad"], eta)
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][0], x.cpu().numpy())
+    assert np.array_equal(res[0][1], res[1][1])
+    assert np.max(np.abs(res[0][1] - Flast)) <= 1e-6 * np.abs(inst.weights).sum()
+
+
+def test_autotune_keeps_results(ffs, mixed, tmp_path):
+    inst, prob = mixed
+    B = 130
+    x = torch.from_numpy(points(inst, B, 41, "uniform")).to(DEV)
+    p0 = ffs.Plan(prob, B)
+    a = to_np(p0.eval(x, want_con=True))
+    cache = str(tmp_path / "tune.json")
+    p1 = ffs.Plan(prob, B, autotune=True, tune_cache=cache)
+    d = p1.describe()
+    assert d["tuned"] and len(d["bins"]["f32"]) >= 12
+    b = to_np(p1.eval(x, want_con=True))
+    assert np.array_equal(a["grad"], b["grad"]) and np.array_equal(a["con_val"], b["con_val"])
+    assert np.max(np.abs(a["F"] - b["F"])) <= 1e-6 * np.abs(inst.weights).sum()
+    p2 = ffs.Plan(prob, B, autotune=True, tune_cache=cache)     # served from the cache file
+    assert p2.describe()["bins"] == d["bins"]
+
+
+def test_debug_nonfinite(ffs):
+    inst = workloads.random_hybrid(20, 1, n_or=10, or_len=(2, 3))
+    prob = ffs.Problem(inst, device=0, flags=ffs.FLAG_DEBUG_CHECKS)
+    plan = ffs.Plan(prob, 4)
+    x = torch.zeros(20, 4, device=DEV)
+    plan.eval(x)
+    x[3, 2] = float("nan")
+    with pytest.raises(ffs.FFSatError) as ei:
+        plan.eval(x)
+    assert ei.value.code == "E_NONFINITE"
+
+
+@pytest.mark.parametrize("B", [1, 2, 63, 64, 65, 129])
+def test_tiny_and_ragged(ffs, B):
+    """n = 1 / m = 1 problems, length-1 constraints, thresholds out of range."""
+    cases = [
+        workloads.assemble(1, [(0, [0], [np.array([-1], np.int32)])]),
+        workloads.assemble(1, [(1, [0], [np.array([1], np.int32)])]),
+        workloads.assemble(1, [(2, [1], [np.array([1], np.int32)])]),
+        workloads.assemble(3, [(2, [0], [np.array([1, -2, 3], np.int32)]),
+                               (2, [4], [np.array([1, 2, 3], np.int32)]),
+                               (2, [3], [np.array([-1, -2, -3], np.int32)]),
+                               (1, [1], [np.array([2], np.int32)])]),
+    ]
+    for inst in cases:
+        prob = ffs.Problem(inst, device=0)
+        plan = ffs.Plan(prob, B)
+        x = workloads.points(inst.n_vars, B, B, dist="mixed_edge")
+        g = _gpu_eval(plan, x)
+        ref = oracle.eval_batch(inst, x.astype(np.float64), want_con=True)
+        e = errors(inst, g, ref)
+        assert max(e.values()) <= TOL32, e
+        out = to_np(plan.round_check(torch.from_numpy(x).to(DEV)))
+        rc = oracle.check(inst, x.astype(np.float64))
+        assert np.array_equal(out["n_sat"], rc["n_sat"]) and np.array_equal(out["U"], rc["U"])
+
+
+def test_device_mismatch(ffs):
+    inst = workloads.random_hybrid(10, 1, n_or=3)
+    with pytest.raises(ffs.FFSatError) as ei:
+        ffs.Problem(inst, device=torch.cuda.device_count())
+    assert ei.value.code == "E_DEVICE_MISMATCH"

@@ -79,18 +79,26 @@ class Instance:
 # --------------------------------------------------------------------------
 
 def _distinct_rows(rng: np.random.Generator, n: int, rows: int, k: int) -> np.ndarray:
-    """rows x k matrix of variable indices in [0, n), distinct within a row."""
+    """rows x k matrix of variable indices in [0, n), distinct within a row
+    (repeated entries of a row are redrawn until the row has none)."""
     if k > n:
         raise ValueError(f"cannot draw {k} distinct variables out of {n}")
     out = rng.integers(0, n, size=(rows, k), dtype=np.int64)
     if k == 1:
         return out
-    while True:
-        s = np.sort(out, axis=1)
-        bad = np.nonzero((s[:, 1:] == s[:, :-1]).any(axis=1))[0]
-        if bad.size == 0:
-            return out
-        out[bad] = rng.integers(0, n, size=(bad.size, k), dtype=np.int64)
+    s = np.sort(out, axis=1)
+    bad = np.nonzero((s[:, 1:] == s[:, :-1]).any(axis=1))[0]
+    for r in bad:
+        row = out[r]
+        while True:
+            _, first = np.unique(row, return_index=True)
+            dup = np.ones(k, dtype=bool)
+            dup[first] = False
+            if not dup.any():
+                break
+            row[dup] = rng.integers(0, n, size=int(dup.sum()), dtype=np.int64)
+        out[r] = row
+    return out
 
 
 def _draw_group(rng, n, count, kmin, kmax, sign_mode):
