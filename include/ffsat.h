@@ -101,7 +101,8 @@ typedef struct {
     int32_t autotune;        /* 1: time tile shapes per bin at plan creation */
     int32_t use_graphs;      /* 1: ffsat_run_steps replays a captured hipGraph */
     const char *tune_cache;  /* JSON file for tuned shapes (NULL = in memory only) */
-    int32_t reserved[8];
+    int32_t reserved[8];     /* reserved[0] = 1: launch all bins on the caller's stream
+                                (no internal side streams); others must be 0 */
 } ffsat_plan_opts;
 
 /* ---- errors ------------------------------------------------------------- */
@@ -171,7 +172,14 @@ ffsat_status ffsat_plan_profile_read(ffsat_plan *plan, int32_t reset, char *buf,
  * given (the polynomial is defined everywhere). */
 ffsat_status ffsat_eval(ffsat_plan *plan, const float *x, float *F, float *grad,
                         float *con_val, void *stream);
-/* Same with double buffers and FP64 computation throughout. */
+/* ffsat_eval plus the exact check of the same point (see ffsat_round_check
+ * for the outputs n_sat, unsat_bits, U), in the same kernels: each literal
+ * is gathered once for both.  With F, grad and con_val all NULL only the
+ * check runs. */
+ffsat_status ffsat_eval_check(ffsat_plan *plan, const float *x, float *F, float *grad,
+                              float *con_val, int32_t *n_sat, uint32_t *unsat_bits, int32_t *U,
+                              void *stream);
+/* Same as ffsat_eval with double buffers and FP64 computation throughout. */
 ffsat_status ffsat_eval_f64(ffsat_plan *plan, const double *x, double *F, double *grad,
                             double *con_val, void *stream);
 

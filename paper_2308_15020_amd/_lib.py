@@ -70,6 +70,7 @@ _SIGS = {
     "ffsat_plan_describe": (I32, [P, C.c_char_p, C.c_size_t]),
     "ffsat_eval": (I32, [P, P, P, P, P, P]),
     "ffsat_eval_f64": (I32, [P, P, P, P, P, P]),
+    "ffsat_eval_check": (I32, [P, P, P, P, P, P, P, P, P]),
     "ffsat_step": (I32, [P, P, P, P, C.c_float, P]),
     "ffsat_step_f64": (I32, [P, P, P, P, C.c_double, P]),
     "ffsat_run_steps": (I32, [P, P, I32, C.c_float, P, P]),

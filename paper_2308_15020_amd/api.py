@@ -102,7 +102,7 @@ class Plan:
     """A batch size B bound to a problem, with its device workspace."""
 
     def __init__(self, problem: Problem, B: int, autotune: bool = False, use_graphs: bool = True,
-                 tune_cache: Optional[str] = None):
+                 tune_cache: Optional[str] = None, side_streams: bool = True):
         self.problem = problem
         self.B = int(B)
         self.device = problem.device
@@ -110,6 +110,7 @@ class Plan:
         o.autotune = 1 if autotune else 0
         o.use_graphs = 1 if use_graphs else 0
         o.tune_cache = tune_cache.encode() if tune_cache else None
+        o.reserved[0] = 0 if side_streams else 1
         h = C.c_void_p()
         check(lib().ffsat_plan_create(problem.handle, self.B, C.byref(o), C.byref(h)))
         self._h = h
@@ -131,22 +132,35 @@ class Plan:
     def _x(self, x, dtype=torch.float32):
         _need(x, (self.n, self.B), dtype, self.device, "x")
 
-    def eval(self, x: torch.Tensor, want_F=True, want_grad=True, want_con=False, out=None) -> dict:
-        """Objective F[B], gradient [n][B], per-constraint values [m][B] at x[n][B]."""
+    def eval(self, x: torch.Tensor, want_F=True, want_grad=True, want_con=False, want_check=False,
+             out=None) -> dict:
+        """Objective F[B], gradient [n][B], per-constraint values [m][B] at x[n][B];
+        with want_check also the exact check of the same point (n_sat, unsat_bits, U)
+        from the same kernels (FP32 only)."""
         dt = x.dtype
         if dt not in (torch.float32, torch.float64):
             raise TypeError("x must be float32 or float64")
         self._x(x, dt)
         out = dict(out or {})
+        dev = self.device
         if want_F and "F" not in out:
-            out["F"] = torch.empty(self.B, dtype=dt, device=self.device)
+            out["F"] = torch.empty(self.B, dtype=dt, device=dev)
         if want_grad and "grad" not in out:
-            out["grad"] = torch.empty(self.n, self.B, dtype=dt, device=self.device)
+            out["grad"] = torch.empty(self.n, self.B, dtype=dt, device=dev)
         if want_con and "con_val" not in out:
-            out["con_val"] = torch.empty(self.m, self.B, dtype=dt, device=self.device)
+            out["con_val"] = torch.empty(self.m, self.B, dtype=dt, device=dev)
         F, g, cv = out.get("F"), out.get("grad"), out.get("con_val")
+        if want_check:
+            if dt != torch.float32:
+                raise TypeError("the fused check is FP32; use round_check for FP64 points")
+            out.setdefault("n_sat", torch.empty(self.B, dtype=torch.int32, device=dev))
+            out.setdefault("unsat_bits", torch.empty(self.B, (self.m + 31) // 32, dtype=torch.int32, device=dev))
+            out.setdefault("U", torch.empty(self.m, dtype=torch.int32, device=dev))
+            check(lib().ffsat_eval_check(self.handle, _ptr(x), _ptr(F), _ptr(g), _ptr(cv), _ptr(out["n_sat"]),
+                                         _ptr(out["unsat_bits"]), _ptr(out["U"]), _stream(dev)))
+            return out
         fn = lib().ffsat_eval if dt == torch.float32 else lib().ffsat_eval_f64
-        check(fn(self.handle, _ptr(x), _ptr(F), _ptr(g), _ptr(cv), _stream(self.device)))
+        check(fn(self.handle, _ptr(x), _ptr(F), _ptr(g), _ptr(cv), _stream(dev)))
         return out
 
     def step(self, x: torch.Tensor, grad: torch.Tensor, eta: float, eta_b: Optional[torch.Tensor] = None):

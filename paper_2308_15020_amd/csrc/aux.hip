@@ -3,108 +3,123 @@
 //    variable-major transpose (fixed order, deterministic), optionally
 //    fused with the projected step (App. A.3, Alg. 5: clip to [-1,1]);
 //  * two-level deterministic sum of objective partials (Def. 3);
-//  * projected step; exact round-and-check (Alg. 1, Thm. 2); adaptive
-//    weights (Prop. 3); weight gradient; small utilities.
+//  * projected step; rounding of the variables (Alg. 1); adaptive weights
+//    (Prop. 3); weight gradient; small utilities.  The exact constraint
+//    check runs inside the evaluation kernels.
 #include "internal.h"
 
 namespace ffsat {
 
 static constexpr int RED_BLOCK = 256;
-static constexpr int F_ROWS_PER_SPLIT = 32;
+static constexpr int F_ROWS_PER_SPLIT = 64;
 
 int f_splits(int rows) { return (rows + F_ROWS_PER_SPLIT - 1) / F_ROWS_PER_SPLIT; }
 
+// Grid: x = variable (uniform per block, so the transpose is read with
+// scalar loads) then one block column per split of objective rows; y =
+// restart chunk of RED_BLOCK.
 template <typename IO, bool STEP>
-__global__ __launch_bounds__(RED_BLOCK) void k_reduce(int n, int B, const int32_t *__restrict__ vptr,
-                                                      const int32_t *__restrict__ vslot,
-                                                      const IO *__restrict__ slot, IO *grad, IO *x,
-                                                      IO eta, int n_gblocks,
-                                                      const IO *__restrict__ fpart, int rows,
-                                                      IO *ftmp)
+__global__ __launch_bounds__(RED_BLOCK) void k_reduce(ReduceArgs<IO> a, int n_grad)
 {
-    const int bid = blockIdx.x;
-    if (bid < n_gblocks) {
-        const int64_t idx = (int64_t)bid * RED_BLOCK + threadIdx.x;
-        if (idx >= (int64_t)n * B) return;
-        const int v = (int)(idx / B);
-        const int b = (int)(idx - (int64_t)v * B);
+    const int bx = blockIdx.x;
+    const int b = blockIdx.y * RED_BLOCK + threadIdx.x;
+    if (b >= a.B) return;
+    const int B = a.B;
+    if (bx < n_grad) {
+        const int v = bx;
+        const int e0 = a.vptr[v], e1 = a.vptr[v + 1];
         double acc = 0.0;
-        const int e1 = vptr[v + 1];
-        for (int e = vptr[v]; e < e1; ++e) acc += (double)slot[(size_t)vslot[e] * B + b];
+        int e = e0;
+        // independent loads first, then the additions in slot order
+        for (; e + 4 <= e1; e += 4) {
+            const IO s0 = a.slot[(size_t)a.vslot[e] * B + b];
+            const IO s1 = a.slot[(size_t)a.vslot[e + 1] * B + b];
+            const IO s2 = a.slot[(size_t)a.vslot[e + 2] * B + b];
+            const IO s3 = a.slot[(size_t)a.vslot[e + 3] * B + b];
+            acc += (double)s0;
+            acc += (double)s1;
+            acc += (double)s2;
+            acc += (double)s3;
+        }
+        for (; e < e1; ++e) acc += (double)a.slot[(size_t)a.vslot[e] * B + b];
+        const size_t idx = (size_t)v * B + b;
         if constexpr (STEP) {
             // same rounding as evaluating the gradient, then the step
             const float g = (float)acc;
-            const float y = __builtin_fmaf(-(float)eta, g, (float)x[idx]);
-            x[idx] = (IO)fminf(fmaxf(y, -1.0f), 1.0f);
+            const float y = __builtin_fmaf(-a.eta, g, a.x_step[idx]);
+            a.x_step[idx] = fminf(fmaxf(y, -1.0f), 1.0f);
         } else {
-            grad[idx] = (IO)acc;
+            a.grad[idx] = (IO)acc;
         }
     } else {
-        // level 1 of the objective sum: one split of F_ROWS_PER_SPLIT rows
-        const int fb = bid - n_gblocks;
-        const int nbb = (B + RED_BLOCK - 1) / RED_BLOCK;
-        const int split = fb / nbb;
-        const int b = (fb - split * nbb) * RED_BLOCK + threadIdx.x;
-        if (b >= B) return;
+        // level 1 of the objective / count sums: one split of F_ROWS_PER_SPLIT rows
+        const int split = bx - n_grad;
         const int r0 = split * F_ROWS_PER_SPLIT;
-        const int r1 = min(rows, r0 + F_ROWS_PER_SPLIT);
-        double acc = 0.0;
-        for (int r = r0; r < r1; ++r) acc += (double)fpart[(size_t)r * B + b];
-        ftmp[(size_t)split * B + b] = (IO)acc;
+        const int r1 = min(a.rows, r0 + F_ROWS_PER_SPLIT);
+        if (a.F != nullptr) {
+            double acc = 0.0;
+#pragma unroll 8
+            for (int r = r0; r < r1; ++r) acc += (double)a.fpart[(size_t)r * B + b];
+            a.ftmp[(size_t)split * B + b] = (IO)acc;
+        }
+        if (a.n_sat != nullptr) {
+            int acc = 0;
+#pragma unroll 8
+            for (int r = r0; r < r1; ++r) acc += a.cpart[(size_t)r * B + b];
+            a.ctmp[(size_t)split * B + b] = acc;
+        }
     }
 }
 
 template <typename IO>
-__global__ __launch_bounds__(RED_BLOCK) void k_fsum2(int B, int splits, const IO *__restrict__ ftmp,
-                                                     IO *F)
+__global__ __launch_bounds__(64) void k_fsum2(ReduceArgs<IO> a, int splits)
 {
-    const int b = blockIdx.x * RED_BLOCK + threadIdx.x;
-    if (b >= B) return;
-    double acc = 0.0;
-    for (int s = 0; s < splits; ++s) acc += (double)ftmp[(size_t)s * B + b];
-    F[b] = (IO)acc;
+    const int b = blockIdx.x * 64 + threadIdx.x;
+    if (b >= a.B) return;
+    if (a.F != nullptr) {
+        double acc = 0.0;
+#pragma unroll 8
+        for (int s = 0; s < splits; ++s) acc += (double)a.ftmp[(size_t)s * a.B + b];
+        a.F[b] = (IO)acc;
+    }
+    if (a.n_sat != nullptr) {
+        int acc = 0;
+#pragma unroll 8
+        for (int s = 0; s < splits; ++s) acc += a.ctmp[(size_t)s * a.B + b];
+        a.n_sat[b] = a.m - acc;
+    }
 }
 
 template <typename IO, bool STEP>
-static hipError_t reduce_impl(int n, int B, const int32_t *vptr, const int32_t *vslot,
-                              const IO *slot, IO *grad, IO *x, IO eta, const IO *fpart, int rows,
-                              IO *ftmp, IO *F, hipStream_t s)
+static hipError_t reduce_impl(const ReduceArgs<IO> &a, hipStream_t s)
 {
-    const bool want_g = STEP ? (x != nullptr) : (grad != nullptr);
-    const int64_t ng = want_g ? ((int64_t)n * B + RED_BLOCK - 1) / RED_BLOCK : 0;
-    const int splits = F ? f_splits(rows) : 0;
-    const int nbb = (B + RED_BLOCK - 1) / RED_BLOCK;
-    const int64_t nf = (int64_t)splits * nbb;
-    if (ng + nf > 0) {
-        hipLaunchKernelGGL((k_reduce<IO, STEP>), dim3((unsigned)(ng + nf)), dim3(RED_BLOCK), 0, s, n,
-                           B, vptr, vslot, slot, grad, x, eta, (int)ng, fpart, rows, ftmp);
+    const bool want_g = STEP ? (a.x_step != nullptr) : (a.grad != nullptr);
+    const int n_grad = want_g ? a.n : 0;
+    const bool rows = a.F != nullptr || a.n_sat != nullptr;
+    const int splits = rows ? f_splits(a.rows) : 0;
+    const int nbb = (a.B + RED_BLOCK - 1) / RED_BLOCK;
+    if (n_grad + splits > 0) {
+        hipLaunchKernelGGL((k_reduce<IO, STEP>), dim3((unsigned)(n_grad + splits), (unsigned)nbb), dim3(RED_BLOCK),
+                           0, s, a, n_grad);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (F) {
-        hipLaunchKernelGGL((k_fsum2<IO>), dim3(nbb), dim3(RED_BLOCK), 0, s, B, splits, ftmp, F);
+    if (rows) {
+        hipLaunchKernelGGL((k_fsum2<IO>), dim3((a.B + 63) / 64), dim3(64), 0, s, a, splits);
         return hipGetLastError();
     }
     return hipSuccess;
 }
 
-hipError_t launch_reduce_f32(int n, int B, const int32_t *vptr, const int32_t *vslot,
-                             const float *slot, float *grad, float *x_step, float eta,
-                             const float *fpart, int rows, float *ftmp, float *F, hipStream_t s)
+hipError_t launch_reduce_f32(const ReduceArgs<float> &r, hipStream_t s)
 {
-    if (x_step)
-        return reduce_impl<float, true>(n, B, vptr, vslot, slot, nullptr, x_step, eta, fpart, rows,
-                                        ftmp, F, s);
-    return reduce_impl<float, false>(n, B, vptr, vslot, slot, grad, nullptr, 0.f, fpart, rows, ftmp,
-                                     F, s);
+    if (r.x_step) return reduce_impl<float, true>(r, s);
+    return reduce_impl<float, false>(r, s);
 }
 
-hipError_t launch_reduce_f64(int n, int B, const int32_t *vptr, const int32_t *vslot,
-                             const double *slot, double *grad, const double *fpart, int rows,
-                             double *ftmp, double *F, hipStream_t s)
+hipError_t launch_reduce_f64(const ReduceArgs<double> &r, hipStream_t s)
 {
-    return reduce_impl<double, false>(n, B, vptr, vslot, slot, grad, nullptr, 0.0, fpart, rows,
-                                      ftmp, F, s);
+    return reduce_impl<double, false>(r, s);
 }
 
 // ---------------------------------------------------------------- projected step
@@ -147,59 +162,7 @@ hipError_t launch_step_f64(int64_t total, int B, double *x, const double *g,
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- round and check
-
-// One wave per (word of 32 consecutive original constraints, 64 restarts).
-// Variable v is True iff x_v < 0; literal -v is True iff v is not.
-template <typename IO>
-__global__ __launch_bounds__(256) void k_check(int m, int B, const IO *__restrict__ x,
-                                               const int32_t *__restrict__ pos,
-                                               const ConDesc *__restrict__ con,
-                                               const int32_t *__restrict__ lit,
-                                               const int32_t *__restrict__ kind,
-                                               const int32_t *__restrict__ param,
-                                               int32_t *n_sat, uint32_t *unsat_bits, int32_t *U)
-{
-    const int lane = threadIdx.x & 63;
-    const int unit = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int n_rb = (B + 63) / 64;
-    const int wm = (m + 31) / 32;
-    if (unit >= wm * n_rb) return;
-    const int word = unit / n_rb;
-    const int rb = unit - word * n_rb;
-    const int b = rb * 64 + lane;
-    const bool bok = b < B;
-    const int bb = bok ? b : B - 1;
-    uint32_t bits = 0;
-    int nsat = 0;
-    for (int q = 0; q < 32; ++q) {
-        const int c = word * 32 + q;
-        if (c >= m) break;
-        const ConDesc d = con[pos[c]];
-        int ntrue = 0;
-        for (int i = 0; i < d.k; ++i) {
-            const int l = lit[d.off + i];
-            const int v = l & 0x7fffffff;
-            const bool vt = x[(size_t)v * B + bb] < IO(0);
-            ntrue += (l < 0) ? (vt ? 0 : 1) : (vt ? 1 : 0);
-        }
-        const int kd = kind[c], pr = param[c];
-        bool sat;
-        if (kd == FFSAT_KIND_OR) sat = ntrue >= 1;
-        else if (kd == FFSAT_KIND_XOR) sat = (ntrue & 1) == (pr & 1);
-        else sat = ntrue >= pr;
-        if (!sat) bits |= 1u << q;
-        nsat += sat ? 1 : 0;
-        if (U != nullptr) {
-            const unsigned long long bal = __ballot((!sat) && bok);
-            if (lane == 0 && bal != 0ull) atomicAdd(&U[c], (int)__popcll(bal));
-        }
-    }
-    if (bok) {
-        if (unsat_bits != nullptr) unsat_bits[(size_t)b * wm + word] = bits;
-        if (n_sat != nullptr) atomicAdd(&n_sat[b], nsat);
-    }
-}
+// ---------------------------------------------------------------- rounding
 
 template <typename IO>
 __global__ void k_assign_bits(int n, int B, const IO *__restrict__ x, uint32_t *bits)
@@ -232,43 +195,20 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
 }
 
 template <typename IO>
-static hipError_t check_impl(const ffsat_problem *p, int B, const IO *x, uint32_t *assign_bits,
-                             int32_t *n_sat, uint32_t *unsat_bits, int32_t *U, hipStream_t s)
+static hipError_t assign_impl(int n, int B, const IO *x, uint32_t *bits, hipStream_t s)
 {
-    const Layout &L = p->lay[IO_F32];
-    hipError_t e;
-    if (U) {
-        if ((e = launch_fill_i32(U, p->m, 0, s)) != hipSuccess) return e;
-    }
-    if (n_sat) {
-        if ((e = launch_fill_i32(n_sat, B, 0, s)) != hipSuccess) return e;
-    }
-    if (n_sat || unsat_bits || U) {
-        const int64_t units = (int64_t)((p->m + 31) / 32) * ((B + 63) / 64);
-        hipLaunchKernelGGL((k_check<IO>), dim3((unsigned)((units + 3) / 4)), dim3(256), 0, s, p->m, B,
-                           x, L.d_pos, L.d_con, L.d_lit, p->d_kind, p->d_param, n_sat, unsat_bits,
-                           U);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (assign_bits) {
-        const int64_t tot = (int64_t)((p->n + 31) / 32) * B;
-        hipLaunchKernelGGL((k_assign_bits<IO>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                           p->n, B, x, assign_bits);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const int64_t tot = (int64_t)((n + 31) / 32) * B;
+    hipLaunchKernelGGL((k_assign_bits<IO>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, B, x, bits);
+    return hipGetLastError();
 }
 
-hipError_t launch_check_f32(const ffsat_problem *p, int B, const float *x, uint32_t *assign_bits,
-                            int32_t *n_sat, uint32_t *unsat_bits, int32_t *U, hipStream_t s)
+hipError_t launch_assign_bits_f32(int n, int B, const float *x, uint32_t *bits, hipStream_t s)
 {
-    return check_impl<float>(p, B, x, assign_bits, n_sat, unsat_bits, U, s);
+    return assign_impl<float>(n, B, x, bits, s);
 }
-hipError_t launch_check_f64(const ffsat_problem *p, int B, const double *x,
-                            uint32_t *assign_bits, int32_t *n_sat, uint32_t *unsat_bits,
-                            int32_t *U, hipStream_t s)
+hipError_t launch_assign_bits_f64(int n, int B, const double *x, uint32_t *bits, hipStream_t s)
 {
-    return check_impl<double>(p, B, x, assign_bits, n_sat, unsat_bits, U, s);
+    return assign_impl<double>(n, B, x, bits, s);
 }
 
 // ---------------------------------------------------------------- adaptive weights

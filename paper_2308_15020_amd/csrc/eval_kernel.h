@@ -1,0 +1,432 @@
+// Kernel template: objective and per-literal gradient of every constraint, for a batch of
+// restarts (paper: Alg. 2 steps i-iii for the value, Eq. chain / Thm. 4 for
+// the reverse traversal; App. B for the transform-free OR/XOR products),
+// fused with the exact round-and-check of the same point (Alg. 1).
+//
+// Mapping on CDNA4 (wave64): a wave owns one restart block and walks a
+// chunk of `cpw` constraints of one bin.  Lane = (restart r, segment j):
+// L adjacent lanes split the literals of a constraint into L segments of
+// s = ceil(k/L) <= SEG literals, so literal values, prefix products and
+// gradient accumulators of a segment live in registers (fully unrolled
+// over SEG; every lane processes exactly SEG positions, padded past the
+// constraint's end, so the arithmetic is straight-line code).  The
+// per-frequency leave-one-out product of literal i is
+//     (prefix inside its segment) * (product of earlier segments)
+//   * (product of later segments) * (suffix inside its segment),
+// the segment products being exchanged by exclusive prefix/suffix scans
+// over the L lanes (DPP row shifts for L <= 16).  Constraint descriptors and
+// coefficient tables are wave-uniform (scalar loads, the next frequency's
+// entry prefetched); literal values are gathered from x[v][b] with restarts
+// contiguous, so a wave reads 64/L consecutive restarts of a variable per
+// load.
+//
+// Per-literal results go to a slot buffer [nnz][B] (value w_c * s_i *
+// dWE_c/dl_i) that a segmented reduction over the variable-major transpose
+// turns into the gradient, in a fixed order (deterministic).  Objective
+// partials and violated-constraint counts go to per-(bin, chunk) rows.
+#pragma once
+#include "internal.h"
+
+namespace ffsat {
+
+template <typename T>
+__device__ __forceinline__ T fmaT(T a, T b, T c);
+template <>
+__device__ __forceinline__ float fmaT<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double fmaT<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// lane (j - D) / (j + D) inside a group of L lanes; only read where valid.
+// Groups of L <= 16 lanes never straddle a DPP row, so row shifts suffice.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+template <int D, int L, typename CT>
+__device__ __forceinline__ CT from_lower(CT v)
+{
+    if constexpr (L <= 16) {
+        if constexpr (sizeof(CT) == 4) return dpp_f32<0x110 + D>(v);
+        else return dpp_f64<0x110 + D>(v);
+    } else {
+        return __shfl_up(v, D, L);
+    }
+}
+template <int D, int L, typename CT>
+__device__ __forceinline__ CT from_upper(CT v)
+{
+    if constexpr (L <= 16) {
+        if constexpr (sizeof(CT) == 4) return dpp_f32<0x100 + D>(v);
+        else return dpp_f64<0x100 + D>(v);
+    } else {
+        return __shfl_down(v, D, L);
+    }
+}
+
+template <typename CT, int L, int D>
+__device__ __forceinline__ void scan_up_cplx(int j, CT &ar, CT &ai)
+{
+    if constexpr (D < L) {
+        const CT yr = from_lower<D, L>(ar), yi = from_lower<D, L>(ai);
+        if (j >= D) {
+            const CT nr = fmaT(yr, ar, -yi * ai);
+            const CT ni = fmaT(yr, ai, yi * ar);
+            ar = nr; ai = ni;
+        }
+        scan_up_cplx<CT, L, 2 * D>(j, ar, ai);
+    }
+}
+template <typename CT, int L, int D>
+__device__ __forceinline__ void scan_down_cplx(int j, CT &br, CT &bi)
+{
+    if constexpr (D < L) {
+        const CT yr = from_upper<D, L>(br), yi = from_upper<D, L>(bi);
+        if (j + D < L) {
+            const CT nr = fmaT(yr, br, -yi * bi);
+            const CT ni = fmaT(yr, bi, yi * br);
+            br = nr; bi = ni;
+        }
+        scan_down_cplx<CT, L, 2 * D>(j, br, bi);
+    }
+}
+
+// exclusive prefix (e) and suffix (s) products of the segment totals t
+template <typename CT, int L>
+__device__ __forceinline__ void group_scan_cplx(int j, CT tr, CT ti, CT &er, CT &ei, CT &sr, CT &si)
+{
+    if constexpr (L == 1) {
+        er = 1; ei = 0; sr = 1; si = 0;
+    } else {
+        CT ar = tr, ai = ti, br = tr, bi = ti;
+        scan_up_cplx<CT, L, 1>(j, ar, ai);
+        scan_down_cplx<CT, L, 1>(j, br, bi);
+        const CT pr = from_lower<1, L>(ar), pi = from_lower<1, L>(ai);
+        const CT qr = from_upper<1, L>(br), qi = from_upper<1, L>(bi);
+        er = j > 0 ? pr : CT(1);
+        ei = j > 0 ? pi : CT(0);
+        sr = j < L - 1 ? qr : CT(1);
+        si = j < L - 1 ? qi : CT(0);
+    }
+}
+
+template <typename CT, int L, int D>
+__device__ __forceinline__ void scan_up_real(int j, CT &a)
+{
+    if constexpr (D < L) {
+        const CT y = from_lower<D, L>(a);
+        if (j >= D) a = y * a;
+        scan_up_real<CT, L, 2 * D>(j, a);
+    }
+}
+template <typename CT, int L, int D>
+__device__ __forceinline__ void scan_down_real(int j, CT &b)
+{
+    if constexpr (D < L) {
+        const CT y = from_upper<D, L>(b);
+        if (j + D < L) b = y * b;
+        scan_down_real<CT, L, 2 * D>(j, b);
+    }
+}
+
+template <typename CT, int L>
+__device__ __forceinline__ void group_scan_real(int j, CT t, CT &pre, CT &suf)
+{
+    if constexpr (L == 1) {
+        pre = 1; suf = 1;
+    } else {
+        CT a = t, b = t;
+        scan_up_real<CT, L, 1>(j, a);
+        scan_down_real<CT, L, 1>(j, b);
+        const CT p = from_lower<1, L>(a), q = from_upper<1, L>(b);
+        pre = j > 0 ? p : CT(1);
+        suf = j < L - 1 ? q : CT(1);
+    }
+}
+
+template <int L>
+__device__ __forceinline__ int group_sum_int(int v)
+{
+#pragma unroll
+    for (int d = 1; d < L; d <<= 1) v += __shfl_xor(v, d, L);
+    return v;
+}
+
+// Read-only inputs are separate __restrict__ arguments: the compiler may
+// then read uniform descriptors and coefficients through the scalar cache.
+template <typename IO, typename CT, int SEG, int L, bool CPLX>
+__global__ __launch_bounds__(256) void k_eval(EvalArgs<IO> a, const IO *__restrict__ xin,
+                                              const ConDesc *__restrict__ con,
+                                              const int32_t *__restrict__ lits,
+                                              const float *__restrict__ wts,
+                                              const TypeT<CT> *__restrict__ types,
+                                              const FreqT<CT> *__restrict__ freqs)
+{
+    constexpr int RPW = 64 / L;
+    const int lane = threadIdx.x & 63;
+    // the wave index is uniform: say so, so that everything derived from it
+    // (constraint descriptors, coefficient tables, loop bounds) stays scalar
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int unit = blockIdx.x * (blockDim.x >> 6) + wave;
+    const int n_chunks = (a.count + a.cpw - 1) / a.cpw;
+    if (unit >= n_chunks * a.n_rb) return;   // whole wave leaves together
+    const int chunk = unit / a.n_rb;
+    const int rb = unit - chunk * a.n_rb;
+    const int j = lane & (L - 1);
+    const int r = lane / L;
+    const int b = rb * RPW + r;
+    const bool bok = b < a.B;
+    const int bb = bok ? b : a.B - 1;
+    const int i0 = j * SEG;
+    CT facc = 0;
+    int nunsat = 0;
+    const int c_begin = chunk * a.cpw;
+    const int c_end = min(c_begin + a.cpw, a.count);
+#pragma unroll 1
+    for (int ci = c_begin; ci < c_end; ++ci) {
+        const ConDesc d = con[a.first + ci];
+        const TypeT<CT> ty = types[d.type];
+        const int k = d.k;
+
+        // step i input: this lane's SEG positions j*SEG .. j*SEG+SEG-1; the
+        // positions past the constraint's end hold the padding value (count
+        // neutral; its factor is divided out of the coefficients on the
+        // host).  Also the rounded truth of each literal (x_v < 0: True).
+        CT lv[SEG];
+        uint32_t negm = 0, tmask = 0;
+#pragma unroll
+        for (int t = 0; t < SEG; ++t) {
+            CT val = ty.pad;
+            const int i = i0 + t;
+            if (i < k) {
+                const int lit = lits[d.off + i];
+                const int v = lit & 0x7fffffff;
+                const IO xr = xin[(size_t)v * a.B + bb];
+                const CT xv = (CT)xr;
+                const bool neg = lit < 0;
+                val = neg ? -xv : xv;
+                negm |= (neg ? 1u : 0u) << t;
+                const bool vt = xr < IO(0);
+                tmask |= ((neg ? !vt : vt) ? 1u : 0u) << t;
+            }
+            lv[t] = val;
+        }
+        if (a.want_check) {
+            const int cnt = group_sum_int<L>(__popc(tmask));
+            const bool sat = d.chk >= 0 ? (cnt >= d.chk) : ((cnt & 1) == (d.chk == -2 ? 1 : 0));
+            const bool uns = !sat && bok && j == 0;
+            nunsat += uns ? 1 : 0;
+            if (a.unsat_bits != nullptr && uns)
+                atomicOr(&a.unsat_bits[(size_t)b * a.wm + (d.orig >> 5)], 1u << (d.orig & 31));
+            if (a.U != nullptr) {
+                const unsigned long long bal = __ballot(uns);
+                if (lane == 0 && bal != 0ull) atomicAdd(&a.U[d.orig], (int)__popcll(bal));
+            }
+        }
+        if (!a.do_value) continue;
+
+        CT gr[SEG];
+#pragma unroll
+        for (int t = 0; t < SEG; ++t) gr[t] = 0;
+        CT we = 0;
+        if constexpr (CPLX) {
+            const int nf = ty.n1 + ty.n2;
+            FreqT<CT> fr = freqs[ty.tab];
+#pragma unroll 1
+            for (int f = 0; f < nf; ++f) {
+                const FreqT<CT> nxt = freqs[ty.tab + f + 1];   // table has one entry of padding
+                const bool form1 = f < ty.n1;
+                const CT tk = fr.tk;
+                CT pr[SEG], pi[SEG];
+                CT Pr = fr.init, Pi = 0;
+                // steps i-ii: affine factors and their running product
+                if (form1) {
+#pragma unroll
+                    for (int t = 0; t < SEG; ++t) {
+                        pr[t] = Pr; pi[t] = Pi;
+                        const CT u = tk * lv[t];
+                        const CT nr = fmaT(Pi, u, Pr);
+                        const CT ni = fmaT(-Pr, u, Pi);
+                        Pr = nr; Pi = ni;
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < SEG; ++t) {
+                        pr[t] = Pr; pi[t] = Pi;
+                        const CT l = lv[t];
+                        const CT nr = fmaT(Pi, l, tk * Pr);
+                        const CT ni = fmaT(-Pr, l, tk * Pi);
+                        Pr = nr; Pi = ni;
+                    }
+                }
+                CT er, ei, sr, si;
+                group_scan_cplx<CT, L>(j, Pr, Pi, er, ei, sr, si);
+                // step iii (lane j == 0 holds the full product T0 * suffix)
+                const CT Gr = fmaT(Pr, sr, -Pi * si);
+                const CT Gi = fmaT(Pr, si, Pi * sr);
+                we += fmaT(fr.c0re, Gr, -fr.c0im * Gi);
+                // reverse traversal seeded with c1 * (other segments).  The
+                // factors are recomputed from an opaque copy of tk so that the
+                // forward products are not kept alive across both passes.
+                CT tkb = tk;
+                asm volatile("" : "+v"(tkb));
+                const CT qr = fmaT(er, sr, -ei * si);
+                const CT qi = fmaT(er, si, ei * sr);
+                CT Sr = fmaT(fr.c1re, qr, -fr.c1im * qi);
+                CT Si = fmaT(fr.c1re, qi, fr.c1im * qr);
+                if (form1) {
+#pragma unroll
+                    for (int t = SEG - 1; t >= 0; --t) {
+                        gr[t] = fmaT(pr[t], Sr, fmaT(-pi[t], Si, gr[t]));
+                        if (t > 0) {
+                            const CT u = tkb * lv[t];
+                            const CT nr = fmaT(Si, u, Sr);
+                            const CT ni = fmaT(-Sr, u, Si);
+                            Sr = nr; Si = ni;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int t = SEG - 1; t >= 0; --t) {
+                        gr[t] = fmaT(pr[t], Sr, fmaT(-pi[t], Si, gr[t]));
+                        if (t > 0) {
+                            const CT l = lv[t];
+                            const CT nr = fmaT(Si, l, tkb * Sr);
+                            const CT ni = fmaT(-Sr, l, tkb * Si);
+                            Sr = nr; Si = ni;
+                        }
+                    }
+                }
+                fr = nxt;
+            }
+        }
+        if (ty.has_real) {
+            // real chain: prod (alpha + beta l); padding factors are exactly 1
+            CT q[SEG];
+            CT P = 1;
+#pragma unroll
+            for (int t = 0; t < SEG; ++t) {
+                q[t] = P;
+                P = P * fmaT(ty.beta, lv[t], ty.alpha);
+            }
+            CT pre, suf;
+            group_scan_real<CT, L>(j, P, pre, suf);
+            we += ty.c0r * (P * suf);
+            CT S = ty.c1r * (pre * suf);
+#pragma unroll
+            for (int t = SEG - 1; t >= 0; --t) {
+                gr[t] = fmaT(q[t], S, gr[t]);
+                if (t > 0) S = S * fmaT(ty.beta, lv[t], ty.alpha);
+            }
+        }
+        we += ty.cst;
+        const CT wc = (CT)wts[d.orig];
+        if (j == 0) facc = fmaT(wc, we, facc);
+        if (a.con_val != nullptr && j == 0 && bok) a.con_val[(size_t)d.orig * a.B + b] = (IO)we;
+        if (a.want_grad && bok) {
+#pragma unroll
+            for (int t = 0; t < SEG; ++t) {
+                const int i = i0 + t;
+                if (i < k) {
+                    const CT gv = ((negm >> t) & 1u) ? -gr[t] : gr[t];
+                    a.slot[(size_t)(d.off + i) * a.B + b] = (IO)(wc * gv);
+                }
+            }
+        }
+    }
+    if (j == 0 && bok) {
+        const size_t row = (size_t)(a.fpart_row0 + chunk) * a.B + b;
+        if (a.do_value) a.fpart[row] = (IO)facc;
+        if (a.want_check) a.cpart[row] = nunsat;
+    }
+}
+
+template <typename IO>
+struct EvalFnT {
+    template <typename CT>
+    using type = void (*)(EvalArgs<IO>, const IO *, const ConDesc *, const int32_t *, const float *,
+                          const TypeT<CT> *, const FreqT<CT> *);
+};
+// type-erased kernel handle: the kernel and the arithmetic type it expects
+template <typename IO>
+struct EvalFn {
+    const void *fn = nullptr;
+    int ct = 0;
+    explicit operator bool() const { return fn != nullptr; }
+};
+
+// Segment shapes: L = 1 with SEG in {4, 8, ..., SMAX}; L >= 2 with SEG in
+// (SMAX/2, SMAX], multiples of 4 (SMAX = 32 for FP32 arithmetic, 16 for FP64).
+template <typename IO, typename CT, int SEG, int L, bool CPLX>
+static EvalFn<IO> handle()
+{
+    EvalFn<IO> h;
+    h.fn = reinterpret_cast<const void *>(&k_eval<IO, CT, SEG, L, CPLX>);
+    h.ct = sizeof(CT) == 4 ? CT_F32 : CT_F64;
+    return h;
+}
+
+template <typename IO, typename CT, bool CPLX, int L>
+static EvalFn<IO> pick_L(int seg)
+{
+    switch (seg) {
+    case 4: if constexpr (L == 1) return handle<IO, CT, 4, L, CPLX>(); break;
+    case 8: if constexpr (L == 1) return handle<IO, CT, 8, L, CPLX>(); break;
+    case 12: if constexpr (L == 1 || sizeof(CT) == 8) return handle<IO, CT, 12, L, CPLX>(); break;
+    case 16: if constexpr (L == 1 || sizeof(CT) == 8) return handle<IO, CT, 16, L, CPLX>(); break;
+    case 20: if constexpr (sizeof(CT) == 4) return handle<IO, CT, 20, L, CPLX>(); break;
+    case 24: if constexpr (sizeof(CT) == 4) return handle<IO, CT, 24, L, CPLX>(); break;
+    case 28: if constexpr (sizeof(CT) == 4) return handle<IO, CT, 28, L, CPLX>(); break;
+    case 32: if constexpr (sizeof(CT) == 4) return handle<IO, CT, 32, L, CPLX>(); break;
+    default: break;
+    }
+    return EvalFn<IO>{};
+}
+
+template <typename IO, typename CT, bool CPLX>
+static EvalFn<IO> pick_seg(int seg, int L)
+{
+    switch (L) {
+    case 1: return pick_L<IO, CT, CPLX, 1>(seg);
+    case 2: return pick_L<IO, CT, CPLX, 2>(seg);
+    case 4: return pick_L<IO, CT, CPLX, 4>(seg);
+    case 8: return pick_L<IO, CT, CPLX, 8>(seg);
+    case 16: return pick_L<IO, CT, CPLX, 16>(seg);
+    case 32: if constexpr (sizeof(CT) == 8) return pick_L<IO, CT, CPLX, 32>(seg); break;
+    default: break;
+    }
+    return EvalFn<IO>{};
+}
+
+template <typename IO>
+static hipError_t launch_fn(EvalFn<IO> fn, const Bin &bin, const EvalArgs<IO> &a, hipStream_t s)
+{
+    if (!fn) return hipErrorInvalidValue;
+    const int n_chunks = (a.count + a.cpw - 1) / a.cpw;
+    const int64_t units = (int64_t)n_chunks * a.n_rb;
+    if (units <= 0) return hipSuccess;
+    const int wpb = bin.wpb;
+    const int64_t blocks = (units + wpb - 1) / wpb;
+    if (fn.ct == CT_F32) {
+        auto k = reinterpret_cast<typename EvalFnT<IO>::template type<float>>(const_cast<void *>(fn.fn));
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, a, a.x, a.con, a.lit, a.w,
+                           reinterpret_cast<const TypeT<float> *>(a.types),
+                           reinterpret_cast<const FreqT<float> *>(a.freqs));
+    } else {
+        auto k = reinterpret_cast<typename EvalFnT<IO>::template type<double>>(const_cast<void *>(fn.fn));
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, a, a.x, a.con, a.lit, a.w,
+                           reinterpret_cast<const TypeT<double> *>(a.types),
+                           reinterpret_cast<const FreqT<double> *>(a.freqs));
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ffsat

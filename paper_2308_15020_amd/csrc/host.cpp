@@ -139,12 +139,11 @@ TypeD real_const(double v) { TypeD t; t.cst = v; t.pad = 1; return t; }
 // the removed factor e^{i k th/2} C^k (or S^k), the padding literals of the
 // segment layout (value +1, count-neutral) and the power-of-two start value
 // of every segment are folded into c0 / c1 here, in long double.
-TypeD dft_type(const std::vector<cld> &hv, int k, int L)
+TypeD dft_type(const std::vector<cld> &hv, int k, int L, int s)
 {
     TypeD t;
     t.cls = CLASS_DFT;
     const int N = k + 1;
-    const int s = (k + L - 1) / L;
     const int npad = L * s - k;
     t.cst = (double)hv[0].real();
     t.pad = 1.0;
@@ -188,20 +187,27 @@ TypeD dft_type(const std::vector<cld> &hv, int k, int L)
     return t;
 }
 
+// Segment shape of a constraint of length k: L lanes (a power of two) of SEG
+// positions each (4, 8, or a multiple of 8 up to 32 for FP32 arithmetic;
+// 4, 8, 12 or 16 for FP64), L * SEG >= k, the smallest such L and then the
+// smallest SEG.  Fewer distinct shapes mean fewer, larger kernel launches.
 void shape_for(int ct, int k, int &seg, int &L)
 {
-    if (ct == CT_F32) seg = k <= 8 ? 8 : (k <= 16 ? 16 : 32);
-    else seg = k <= 8 ? 8 : 16;
-    const int need = (k + seg - 1) / seg;
+    const int smax = ct == CT_F32 ? 32 : 16;
     L = 1;
-    while (L < need) L <<= 1;
+    while ((k + L - 1) / L > smax) L <<= 1;
+    const int s = (k + L - 1) / L;
+    if (s <= 4) seg = 4;
+    else if (s <= 8) seg = 8;
+    else if (ct == CT_F32) seg = ((s + 7) / 8) * 8;
+    else seg = ((s + 3) / 4) * 4;
 }
 
 struct TypeKey {
-    int cls, ct, kind, param, k, L;
+    int cls, ct, kind, param, k, L, seg;
     bool operator<(const TypeKey &o) const
     {
-        return std::tie(cls, ct, kind, param, k, L) < std::tie(o.cls, o.ct, o.kind, o.param, o.k, o.L);
+        return std::tie(cls, ct, kind, param, k, L, seg) < std::tie(o.cls, o.ct, o.kind, o.param, o.k, o.L, o.seg);
     }
 };
 
@@ -331,10 +337,10 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
         if (!eval_variant_exists(io, ct, cls, seg, L))
             return fail(FFSAT_E_UNSUPPORTED, "no kernel variant for constraint %d (k=%d)", c, k);
         TypeKey tk;
-        if (cls == CLASS_REAL) tk = TypeKey{cls, ct, rk, rparam, 0, 0};
+        if (cls == CLASS_REAL) tk = TypeKey{cls, ct, rk, rparam, 0, 0, 0};
         else {
             int nprm = kind == FFSAT_KIND_XOR ? (prm & 1) : (kind == FFSAT_KIND_OR ? 0 : prm);
-            tk = TypeKey{cls, ct, kind, nprm, k, L};
+            tk = TypeKey{cls, ct, kind, nprm, k, L, seg};
         }
         auto it = type_index.find(tk);
         int ti;
@@ -344,7 +350,7 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
                 auto key = std::make_tuple(tk.kind, tk.param, k);
                 auto mh = memo.find(key);
                 if (mh == memo.end()) mh = memo.emplace(key, conj_coeffs(tk.kind, tk.param, k)).first;
-                td = dft_type(mh->second, k, L);
+                td = dft_type(mh->second, k, L, seg);
             }
             else if (rk == RK_OR) td = real_or();
             else if (rk == RK_XOR) td = real_xor(rparam);
@@ -380,6 +386,7 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
             const TypeD &td = types[(size_t)ti];
             const double nfc = (double)(td.n1 + td.n2);
             b.flops += 14.0 * k * nfc + 4.0 * nfc + (td.has_real ? 8.0 * k : 0.0);
+            b.exec_pos += (double)L * seg;
             b.bytes += (io == IO_F32 ? 8.0 : 16.0) * k;
         }
         b.count += 1;
@@ -418,7 +425,9 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
     int64_t off = 0;
     for (int q = 0; q < m; ++q) {
         const Item &it = items[(size_t)q];
-        con[(size_t)q] = ConDesc{(int32_t)off, it.k, it.type, it.c};
+        const int kd = d->kinds[it.c], pm = d->params[it.c];
+        const int chk = kd == FFSAT_KIND_OR ? 1 : (kd == FFSAT_KIND_XOR ? ((pm & 1) ? -2 : -1) : std::max(pm, 0));
+        con[(size_t)q] = ConDesc{(int32_t)off, it.k, it.type, it.c, chk, 0, 0, 0};
         pos[(size_t)it.c] = q;
         for (int i = 0; i < it.k; ++i) {
             const int32_t l = d->lits[d->con_ptr[it.c] + i];
@@ -453,10 +462,9 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
             f64.push_back(FreqF64{f.tk, f.init, f.c0re, f.c0im, f.c1re, f.c1im, 0.0, 0.0});
         }
     }
-    if (f32.empty()) {
-        f32.push_back(FreqF32{});
-        f64.push_back(FreqF64{});
-    }
+    // one entry of padding: the kernels prefetch the entry after a type's last
+    f32.push_back(FreqF32{});
+    f64.push_back(FreqF64{});
     Ly.n_types = (int)types.size();
     Ly.n_freqs = (int64_t)f64.size();
     ffsat_status st;
@@ -581,6 +589,13 @@ static ffsat_status ensure_workspace(ffsat_plan *pl, int io)
     HIPCHK(hipMalloc(&pl->d_fpart[io], fpart));
     HIPCHK(hipMalloc(&pl->d_ftmp[io], ftmp));
     pl->device_bytes += (int64_t)(slot + fpart + ftmp);
+    if (!pl->d_cpart) {
+        const size_t cp = (size_t)pl->p->m * B * sizeof(int32_t);
+        const size_t ct = (size_t)f_splits(pl->p->m) * B * sizeof(int32_t);
+        HIPCHK(hipMalloc(&pl->d_cpart, cp));
+        HIPCHK(hipMalloc(&pl->d_ctmp, ct));
+        pl->device_bytes += (int64_t)(cp + ct);
+    }
     return FFSAT_OK;
 }
 
@@ -641,8 +656,12 @@ static EvalArgs<IO> base_args(ffsat_plan *pl, int io, const IO *x, IO *con_val, 
     a.con = Ly.d_con;
     a.lit = Ly.d_lit;
     a.w = p->d_w;
+    a.cpart = pl->d_cpart;
     a.B = pl->B;
+    a.wm = (p->m + 31) / 32;
     a.want_grad = want_grad ? 1 : 0;
+    a.do_value = 1;
+    a.want_check = 0;
     return a;
 }
 
@@ -682,14 +701,26 @@ static void prof_end(ffsat_plan *pl, hipStream_t s, ProfRec &r)
     pl->prof_pending.push_back(r);
 }
 
+// Launches every bin of the evaluation.  With side streams, the bins are
+// spread over them (heaviest first, each to the least loaded stream) after a
+// fork event on s, and s waits for all of them: independent bins overlap,
+// and under graph capture they become parallel branches.
 template <typename IO>
 static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream_t s)
 {
     const Layout &Ly = pl->p->lay[io];
-    const bool prof = prof_active(pl, s);
+    const std::vector<Bin> &bins = pl->bins[io];
+    const bool fork = pl->side[0] != nullptr && bins.size() > 1;
+    hipError_t e;
+    constexpr int NS = ffsat_plan::N_SIDE + 1;   // slot 0 is the caller's stream
+    double load[NS] = {};
+    bool used[NS] = {};
+    if (fork) {
+        if ((e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return e;
+    }
     int row0 = 0;
     int bi = 0;
-    for (const Bin &b : pl->bins[io]) {
+    for (const Bin &b : bins) {
         a.first = b.first;
         a.count = b.count;
         a.cpw = b.cpw;
@@ -697,17 +728,56 @@ static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream
         a.fpart_row0 = row0;
         a.types = b.ct == CT_F32 ? (const void *)Ly.d_t32 : (const void *)Ly.d_t64;
         a.freqs = b.ct == CT_F32 ? (const void *)Ly.d_f32 : (const void *)Ly.d_f64;
-        hipError_t e;
+        hipStream_t bs = s;
+        if (fork) {
+            int q = 0;
+            for (int i = 1; i < NS; ++i)
+                if (load[i] < load[q]) q = i;
+            if (q > 0 && !used[q]) {
+                if ((e = hipStreamWaitEvent(pl->side[q - 1], pl->ev_fork, 0)) != hipSuccess) return e;
+            }
+            used[q] = true;
+            load[q] += b.cost * (double)pl->B + 5.0e6;   // work plus a per-launch latency term
+            bs = q == 0 ? s : pl->side[q - 1];
+        }
         ProfRec rec;
-        prof_begin(pl, s, prof, rec, io, bi);
-        if constexpr (sizeof(IO) == 4) e = launch_eval_bin_f32(b, a, s);
-        else e = launch_eval_bin_f64(b, a, s);
-        prof_end(pl, s, rec);
+        prof_begin(pl, bs, prof_active(pl, s), rec, io, bi);
+        if constexpr (sizeof(IO) == 4) e = launch_eval_bin_f32(b, a, bs);
+        else e = launch_eval_bin_f64(b, a, bs);
+        prof_end(pl, bs, rec);
         if (e != hipSuccess) return e;
         row0 += (b.count + b.cpw - 1) / b.cpw;
         ++bi;
     }
+    if (fork) {
+        for (int q = 1; q < NS; ++q) {
+            if (!used[q]) continue;
+            if ((e = hipEventRecord(pl->ev_join[q - 1], pl->side[q - 1])) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s, pl->ev_join[q - 1], 0)) != hipSuccess) return e;
+        }
+    }
     return hipSuccess;
+}
+
+// Constraints per wave: enough waves per bin to cover the chip (the
+// autotuner refines this).  Root-of-unity bins keep one constraint per wave.
+static void default_shapes(ffsat_plan *pl)
+{
+    for (int io = 0; io < 2; ++io) {
+        for (Bin &b : pl->bins[io]) {
+            b.wpb = 4;
+            if (b.cls == CLASS_DFT) {
+                b.cpw = 1;
+                continue;
+            }
+            const int cap = b.maxk <= 8 ? 16 : (b.maxk <= 32 ? 8 : 2);
+            const int64_t n_rb = (pl->B + (64 / b.L) - 1) / (64 / b.L);
+            const int64_t target = 4096;   // waves
+            int64_t cpw = ((int64_t)b.count * n_rb) / target;
+            b.cpw = (int)std::max<int64_t>(1, std::min<int64_t>(cap, cpw));
+        }
+        pl->fpart_rows[io] = fpart_rows_of(pl->bins[io]);
+    }
 }
 
 extern "C" ffsat_status ffsat_plan_tune(ffsat_plan *pl, void *stream)
@@ -728,6 +798,7 @@ extern "C" ffsat_status ffsat_plan_tune(ffsat_plan *pl, void *stream)
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     EvalArgs<float> a = base_args<float>(pl, IO_F32, pl->d_scratch_x, nullptr, true);
+    a.want_check = 1;
     const Layout &Ly = p->lay[IO_F32];
     bool dirty = false;
     for (Bin &b : pl->bins[IO_F32]) {
@@ -794,14 +865,22 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
     pl->B = B;
     pl->bins[0] = p->lay[0].bins;
     pl->bins[1] = p->lay[1].bins;
-    pl->fpart_rows[0] = fpart_rows_of(pl->bins[0]);
-    pl->fpart_rows[1] = fpart_rows_of(pl->bins[1]);
+    default_shapes(pl);
     pl->use_graphs = opts ? opts->use_graphs != 0 : true;
     if (opts && opts->tune_cache) pl->tune_cache = opts->tune_cache;
     ffsat_status st = ensure_workspace(pl, IO_F32);
     if (st == FFSAT_OK) {
         hipError_t e = hipMalloc(&pl->d_flag, sizeof(int32_t));
         if (e != hipSuccess) st = fail(FFSAT_E_NOMEM, "hipMalloc flag: %s", hipGetErrorString(e));
+    }
+    if (st == FFSAT_OK && !(opts && opts->reserved[0] == 1)) {
+        // side streams (default priority) for concurrent bins; reserved[0] == 1 disables them
+        hipError_t e = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming);
+        for (int q = 0; q < ffsat_plan::N_SIDE && e == hipSuccess; ++q) {
+            e = hipStreamCreateWithFlags(&pl->side[q], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_join[q], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) st = fail(FFSAT_E_HIP, "side streams: %s", hipGetErrorString(e));
     }
     if (st == FFSAT_OK && opts && opts->autotune) {
         st = ffsat_plan_tune(pl, nullptr);
@@ -871,8 +950,15 @@ extern "C" ffsat_status ffsat_plan_destroy(ffsat_plan *pl)
         (void)hipFree(pl->d_ftmp[io]);
     }
     (void)hipFree(pl->d_flag);
+    (void)hipFree(pl->d_cpart);
+    (void)hipFree(pl->d_ctmp);
     (void)hipFree(pl->d_scratch_x);
     if (pl->cap) (void)hipStreamDestroy(pl->cap);
+    for (int q = 0; q < ffsat_plan::N_SIDE; ++q) {
+        if (pl->side[q]) (void)hipStreamDestroy(pl->side[q]);
+        if (pl->ev_join[q]) (void)hipEventDestroy(pl->ev_join[q]);
+    }
+    if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
     delete pl;
     return FFSAT_OK;
 }
@@ -890,7 +976,8 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
               << (b.ct == CT_F32 ? "f32" : "f64") << "\", \"seg\": " << b.seg << ", \"L\": " << b.L
               << ", \"first\": " << b.first << ", \"count\": " << b.count << ", \"maxk\": " << b.maxk
               << ", \"lits\": " << b.lits << ", \"cost\": " << b.cost << ", \"flops_per_restart\": " << b.flops
-              << ", \"bytes_per_restart\": " << b.bytes << ", \"cpw\": " << b.cpw
+              << ", \"bytes_per_restart\": " << b.bytes << ", \"positions_per_restart\": " << b.exec_pos
+              << ", \"cpw\": " << b.cpw
               << ", \"wpb\": " << b.wpb << "}";
         }
         o << "]";
@@ -920,6 +1007,54 @@ static ffsat_status check_finite(ffsat_plan *pl, const IO *x, hipStream_t s)
     return FFSAT_OK;
 }
 
+// One evaluation pass: optional value/gradient/objective outputs, optional
+// exact check of the same point, optional fused projected step.
+template <typename IO>
+static ffsat_status run_eval(ffsat_plan *pl, const IO *x, IO *F, IO *grad, IO *con_val, int32_t *n_sat,
+                             uint32_t *unsat_bits, int32_t *U, bool do_value, float *x_step, float eta,
+                             hipStream_t s)
+{
+    const int io = sizeof(IO) == 4 ? IO_F32 : IO_F64;
+    const ffsat_problem *p = pl->p;
+    const bool want_check = n_sat || unsat_bits || U;
+    if (!do_value && !want_check) return FFSAT_OK;
+    if (U) HIPCHK(launch_fill_i32(U, p->m, 0, s));
+    if (unsat_bits) HIPCHK(launch_fill_i32((int32_t *)unsat_bits, (int64_t)((p->m + 31) / 32) * pl->B, 0, s));
+    const bool grad_slots = do_value && (grad != nullptr || x_step != nullptr);
+    EvalArgs<IO> a = base_args<IO>(pl, io, x, do_value ? con_val : nullptr, grad_slots);
+    a.do_value = do_value ? 1 : 0;
+    a.want_check = want_check ? 1 : 0;
+    a.unsat_bits = unsat_bits;
+    a.U = U;
+    HIPCHK(enqueue_bins<IO>(pl, io, a, s));
+    const Layout &Ly = p->lay[io];
+    ReduceArgs<IO> r{};
+    r.n = p->n;
+    r.B = pl->B;
+    r.m = p->m;
+    r.vptr = Ly.d_vptr;
+    r.vslot = Ly.d_vslot;
+    r.slot = (const IO *)pl->d_slot[io];
+    r.grad = do_value ? grad : nullptr;
+    r.x_step = do_value ? x_step : nullptr;
+    r.eta = eta;
+    r.fpart = (const IO *)pl->d_fpart[io];
+    r.cpart = pl->d_cpart;
+    r.rows = pl->fpart_rows[io];
+    r.ftmp = (IO *)pl->d_ftmp[io];
+    r.ctmp = pl->d_ctmp;
+    r.F = do_value ? F : nullptr;
+    r.n_sat = n_sat;
+    ProfRec rec;
+    prof_begin(pl, s, prof_active(pl, s), rec, io, -1);
+    hipError_t e;
+    if constexpr (sizeof(IO) == 4) e = launch_reduce_f32(r, s);
+    else e = launch_reduce_f64(r, s);
+    prof_end(pl, s, rec);
+    HIPCHK(e);
+    return FFSAT_OK;
+}
+
 extern "C" ffsat_status ffsat_eval(ffsat_plan *pl, const float *x, float *F, float *grad, float *con_val, void *stream)
 {
     if (!pl || !x) return fail(FFSAT_E_INVALID_ARG, "NULL plan or x");
@@ -928,17 +1063,19 @@ extern "C" ffsat_status ffsat_eval(ffsat_plan *pl, const float *x, float *F, flo
     if (st != FFSAT_OK) return st;
     if ((st = check_finite<float>(pl, x, s)) != FFSAT_OK) return st;
     if (!F && !grad && !con_val) return FFSAT_OK;
-    EvalArgs<float> a = base_args<float>(pl, IO_F32, x, con_val, grad != nullptr);
-    HIPCHK(enqueue_bins<float>(pl, IO_F32, a, s));
-    const Layout &Ly = pl->p->lay[IO_F32];
-    ProfRec rec;
-    prof_begin(pl, s, prof_active(pl, s), rec, IO_F32, -1);
-    hipError_t e = launch_reduce_f32(pl->p->n, pl->B, Ly.d_vptr, Ly.d_vslot, (const float *)pl->d_slot[0], grad,
-                                     nullptr, 0.f, (const float *)pl->d_fpart[0], pl->fpart_rows[0],
-                                     (float *)pl->d_ftmp[0], F, s);
-    prof_end(pl, s, rec);
-    HIPCHK(e);
-    return FFSAT_OK;
+    return run_eval<float>(pl, x, F, grad, con_val, nullptr, nullptr, nullptr, true, nullptr, 0.f, s);
+}
+
+extern "C" ffsat_status ffsat_eval_check(ffsat_plan *pl, const float *x, float *F, float *grad, float *con_val,
+                                         int32_t *n_sat, uint32_t *unsat_bits, int32_t *U, void *stream)
+{
+    if (!pl || !x) return fail(FFSAT_E_INVALID_ARG, "NULL plan or x");
+    hipStream_t s = (hipStream_t)stream;
+    ffsat_status st = ensure_workspace(pl, IO_F32);
+    if (st != FFSAT_OK) return st;
+    if ((st = check_finite<float>(pl, x, s)) != FFSAT_OK) return st;
+    const bool value = F || grad || con_val;
+    return run_eval<float>(pl, x, F, grad, con_val, n_sat, unsat_bits, U, value, nullptr, 0.f, s);
 }
 
 extern "C" ffsat_status ffsat_eval_f64(ffsat_plan *pl, const double *x, double *F, double *grad, double *con_val,
@@ -950,16 +1087,7 @@ extern "C" ffsat_status ffsat_eval_f64(ffsat_plan *pl, const double *x, double *
     if (st != FFSAT_OK) return st;
     if ((st = check_finite<double>(pl, x, s)) != FFSAT_OK) return st;
     if (!F && !grad && !con_val) return FFSAT_OK;
-    EvalArgs<double> a = base_args<double>(pl, IO_F64, x, con_val, grad != nullptr);
-    HIPCHK(enqueue_bins<double>(pl, IO_F64, a, s));
-    const Layout &Ly = pl->p->lay[IO_F64];
-    ProfRec rec;
-    prof_begin(pl, s, prof_active(pl, s), rec, IO_F64, -1);
-    hipError_t e = launch_reduce_f64(pl->p->n, pl->B, Ly.d_vptr, Ly.d_vslot, (const double *)pl->d_slot[1], grad,
-                                     (const double *)pl->d_fpart[1], pl->fpart_rows[1], (double *)pl->d_ftmp[1], F, s);
-    prof_end(pl, s, rec);
-    HIPCHK(e);
-    return FFSAT_OK;
+    return run_eval<double>(pl, x, F, grad, con_val, nullptr, nullptr, nullptr, true, nullptr, 0.f, s);
 }
 
 extern "C" ffsat_status ffsat_step(ffsat_plan *pl, float *x, const float *grad, const float *eta_B, float eta,
@@ -980,16 +1108,8 @@ extern "C" ffsat_status ffsat_step_f64(ffsat_plan *pl, double *x, const double *
 
 static hipError_t enqueue_step_iter(ffsat_plan *pl, float *x, float eta, float *F, hipStream_t s)
 {
-    EvalArgs<float> a = base_args<float>(pl, IO_F32, x, nullptr, true);
-    hipError_t e = enqueue_bins<float>(pl, IO_F32, a, s);
-    if (e != hipSuccess) return e;
-    const Layout &Ly = pl->p->lay[IO_F32];
-    ProfRec rec;
-    prof_begin(pl, s, prof_active(pl, s), rec, IO_F32, -1);
-    e = launch_reduce_f32(pl->p->n, pl->B, Ly.d_vptr, Ly.d_vslot, (const float *)pl->d_slot[0], nullptr, x, eta,
-                          (const float *)pl->d_fpart[0], pl->fpart_rows[0], (float *)pl->d_ftmp[0], F, s);
-    prof_end(pl, s, rec);
-    return e;
+    const ffsat_status st = run_eval<float>(pl, x, F, nullptr, nullptr, nullptr, nullptr, nullptr, true, x, eta, s);
+    return st == FFSAT_OK ? hipSuccess : hipErrorUnknown;
 }
 
 extern "C" ffsat_status ffsat_run_steps(ffsat_plan *pl, float *x, int32_t T, float eta, float *F_last, void *stream)
@@ -1039,7 +1159,13 @@ extern "C" ffsat_status ffsat_round_check(ffsat_plan *pl, const float *x, uint32
                                           uint32_t *unsat_bits, int32_t *U, void *stream)
 {
     if (!pl || !x) return fail(FFSAT_E_INVALID_ARG, "NULL plan or x");
-    HIPCHK(launch_check_f32(pl->p, pl->B, x, assign_bits, n_sat, unsat_bits, U, (hipStream_t)stream));
+    hipStream_t s = (hipStream_t)stream;
+    ffsat_status st = ensure_workspace(pl, IO_F32);
+    if (st != FFSAT_OK) return st;
+    if ((st = run_eval<float>(pl, x, nullptr, nullptr, nullptr, n_sat, unsat_bits, U, false, nullptr, 0.f, s)) !=
+        FFSAT_OK)
+        return st;
+    if (assign_bits) HIPCHK(launch_assign_bits_f32(pl->p->n, pl->B, x, assign_bits, s));
     return FFSAT_OK;
 }
 
@@ -1047,7 +1173,13 @@ extern "C" ffsat_status ffsat_round_check_f64(ffsat_plan *pl, const double *x, u
                                               int32_t *n_sat, uint32_t *unsat_bits, int32_t *U, void *stream)
 {
     if (!pl || !x) return fail(FFSAT_E_INVALID_ARG, "NULL plan or x");
-    HIPCHK(launch_check_f64(pl->p, pl->B, x, assign_bits, n_sat, unsat_bits, U, (hipStream_t)stream));
+    hipStream_t s = (hipStream_t)stream;
+    ffsat_status st = ensure_workspace(pl, IO_F64);
+    if (st != FFSAT_OK) return st;
+    if ((st = run_eval<double>(pl, x, nullptr, nullptr, nullptr, n_sat, unsat_bits, U, false, nullptr, 0.f, s)) !=
+        FFSAT_OK)
+        return st;
+    if (assign_bits) HIPCHK(launch_assign_bits_f64(pl->p->n, pl->B, x, assign_bits, s));
     return FFSAT_OK;
 }
 

@@ -45,6 +45,9 @@ struct ConDesc {
     int32_t k;     // length
     int32_t type;  // index into the type tables
     int32_t orig;  // original constraint index
+    int32_t chk;   // exact check: >= 0: satisfied iff #true >= chk;
+                   // -1: iff #true even; -2: iff #true odd
+    int32_t pad0, pad1, pad2;
 };
 
 struct Bin {
@@ -57,6 +60,7 @@ struct Bin {
     int64_t lits = 0;           // literal slots in the bin
     double flops = 0;           // algorithmic FLOPs per restart (value + gradient)
     double bytes = 0;           // algorithmic HBM bytes per restart (gathers + slot writes)
+    double exec_pos = 0;        // literal positions executed per restart (with padding)
     int cpw = 1, wpb = 4;       // tile shape: constraints per wave, waves per block
 };
 
@@ -105,12 +109,16 @@ struct EvalArgs {
     IO *slot;
     IO *fpart;
     IO *con_val;
+    int32_t *cpart;        // violated-constraint count rows (with fpart's row layout)
+    uint32_t *unsat_bits;  // [B][wm] or null (pre-zeroed)
+    int32_t *U;            // [m] or null (pre-zeroed)
     const ConDesc *con;
     const int32_t *lit;
     const float *w;
     const void *types;
     const void *freqs;
-    int B, first, count, cpw, n_rb, fpart_row0, want_grad, pad_;
+    int B, first, count, cpw, n_rb, fpart_row0;
+    int want_grad, do_value, want_check, wm;
 };
 
 struct GraphKey {
@@ -135,10 +143,18 @@ struct ffsat_plan {
     void *d_slot[2] = {nullptr, nullptr};
     void *d_fpart[2] = {nullptr, nullptr};
     void *d_ftmp[2] = {nullptr, nullptr};
+    int32_t *d_cpart = nullptr;      // violated-count rows (shared by both precisions)
+    int32_t *d_ctmp = nullptr;
     int fpart_rows[2] = {0, 0};
     int32_t *d_flag = nullptr;       // debug non-finite flag
     float *d_scratch_x = nullptr;    // autotuner input
     hipStream_t cap = nullptr;       // capture stream for graphs
+    // three side streams: with the caller's stream, one per hardware queue
+    // of HIP's default of four per process
+    static constexpr int N_SIDE = 3;
+    hipStream_t side[N_SIDE] = {};   // bins run concurrently on these (fork/join)
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[N_SIDE] = {};
     bool use_graphs = true;
     bool tuned = false;
     std::string tune_cache;
@@ -157,21 +173,33 @@ hipError_t launch_eval_bin_f32(const Bin &bin, const EvalArgs<float> &a, hipStre
 hipError_t launch_eval_bin_f64(const Bin &bin, const EvalArgs<double> &a, hipStream_t s);
 bool eval_variant_exists(int io, int ct, int cls, int seg, int L);
 
-hipError_t launch_reduce_f32(int n, int B, const int32_t *vptr, const int32_t *vslot,
-                             const float *slot, float *grad, float *x_step, float eta,
-                             const float *fpart, int rows, float *ftmp, float *F, hipStream_t s);
-hipError_t launch_reduce_f64(int n, int B, const int32_t *vptr, const int32_t *vslot,
-                             const double *slot, double *grad, const double *fpart, int rows,
-                             double *ftmp, double *F, hipStream_t s);
+// Reduction after the evaluation kernels: gradient (or fused projected step
+// when x_step != null) over the variable-major transpose, objective rows into
+// F, violated-count rows into n_sat = m - sum.
+template <typename IO>
+struct ReduceArgs {
+    int n, B, m;
+    const int32_t *vptr, *vslot;
+    const IO *slot;
+    IO *grad;
+    float *x_step;
+    float eta;
+    const IO *fpart;
+    const int32_t *cpart;
+    int rows;
+    IO *ftmp;
+    int32_t *ctmp;
+    IO *F;
+    int32_t *n_sat;
+};
+hipError_t launch_reduce_f32(const ReduceArgs<float> &r, hipStream_t s);
+hipError_t launch_reduce_f64(const ReduceArgs<double> &r, hipStream_t s);
 hipError_t launch_step_f32(int64_t total, int B, float *x, const float *g, const float *eta_b,
                            float eta, hipStream_t s);
 hipError_t launch_step_f64(int64_t total, int B, double *x, const double *g,
                            const double *eta_b, double eta, hipStream_t s);
-hipError_t launch_check_f32(const ffsat_problem *p, int B, const float *x, uint32_t *assign_bits,
-                            int32_t *n_sat, uint32_t *unsat_bits, int32_t *U, hipStream_t s);
-hipError_t launch_check_f64(const ffsat_problem *p, int B, const double *x,
-                            uint32_t *assign_bits, int32_t *n_sat, uint32_t *unsat_bits,
-                            int32_t *U, hipStream_t s);
+hipError_t launch_assign_bits_f32(int n, int B, const float *x, uint32_t *bits, hipStream_t s);
+hipError_t launch_assign_bits_f64(int n, int B, const double *x, uint32_t *bits, hipStream_t s);
 hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, hipStream_t s);
 hipError_t launch_wgrad(int m, int B, const float *con_val, const float *gF, float *gw,
                         hipStream_t s);

@@ -138,6 +138,33 @@ def test_round_check_bit_exact(ffs, mixed, dist):
         assert np.array_equal(out["assign_bits"].view(np.uint32), ref["assign_bits"])
 
 
+@pytest.mark.parametrize("dist", ["uniform", "mixed_edge"])
+def test_eval_check_fused(ffs, mixed, dist):
+    """Value, gradient and exact check of the same point from one pass."""
+    inst, prob = mixed
+    B = 90
+    plan = ffs.Plan(prob, B)
+    x = points(inst, B, 51, dist)
+    xt = torch.from_numpy(x).to(DEV)
+    fused = to_np(plan.eval(xt, want_con=True, want_check=True))
+    plain = to_np(plan.eval(xt, want_con=True))
+    for k in ("F", "grad", "con_val"):
+        assert np.array_equal(fused[k], plain[k]), k
+    ref = oracle.check(inst, x.astype(np.float64))
+    assert np.array_equal(fused["n_sat"], ref["n_sat"])
+    assert np.array_equal(fused["U"], ref["U"])
+    assert np.array_equal(fused["unsat_bits"].view(np.uint32), ref["unsat_bits"])
+    # check only (no value outputs requested)
+    import ctypes as C
+    from paper_2308_15020_amd._lib import check as chk, lib
+    ns = torch.empty(B, dtype=torch.int32, device=DEV)
+    U = torch.empty(inst.m, dtype=torch.int32, device=DEV)
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    chk(lib().ffsat_eval_check(plan.handle, C.c_void_p(xt.data_ptr()), None, None, None,
+                               C.c_void_p(ns.data_ptr()), None, C.c_void_p(U.data_ptr()), s))
+    assert np.array_equal(ns.cpu().numpy(), ref["n_sat"]) and np.array_equal(U.cpu().numpy(), ref["U"])
+
+
 def test_weights_erwa_and_weight_gradient(ffs, mixed):
     inst, prob = mixed
     B = 96
@@ -169,14 +196,19 @@ def test_weights_erwa_and_weight_gradient(ffs, mixed):
 
 
 def test_determinism(ffs, mixed):
+    """Bitwise-equal results on repeated calls, with bins on side streams or
+    all on one stream."""
     inst, prob = mixed
     B = 128
     plan = ffs.Plan(prob, B)
+    one = ffs.Plan(prob, B, side_streams=False)
     x = torch.from_numpy(points(inst, B, 5, "uniform")).to(DEV)
-    a = to_np(plan.eval(x, want_con=True))
-    b = to_np(plan.eval(x, want_con=True))
+    a = to_np(plan.eval(x, want_con=True, want_check=True))
+    b = to_np(plan.eval(x, want_con=True, want_check=True))
+    c = to_np(one.eval(x, want_con=True, want_check=True))
     for k in a:
         assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], c[k]), k
 
 
 def test_run_steps_graph_equals_eager_loop(ffs, mixed):
