@@ -113,11 +113,10 @@ def main():
     eta = C.c_float(args.eta)
 
     def step():
-        # objective, gradient and the exact check of x_t in one pass, the
-        # adaptive weights from the check, then the projected step to x_{t+1}
-        check(L.ffsat_eval_check(ph, p(x), p(out["F"]), p(out["grad"]), None, p(n_sat), None, p(U), stream))
+        # objective, gradient, exact check of x_t and the projected step to
+        # x_{t+1} in one pass, then the adaptive weights from the check
+        check(L.ffsat_eval_step(ph, p(x), eta, p(out["F"]), p(n_sat), p(U), stream))
         check(L.ffsat_erwa_update(ph, p(U), C.c_float(0.4), stream))
-        check(L.ffsat_step(ph, p(x), p(out["grad"]), None, eta, stream))
 
     for _ in range(args.warmup):
         step()

@@ -179,6 +179,14 @@ ffsat_status ffsat_eval(ffsat_plan *plan, const float *x, float *F, float *grad,
 ffsat_status ffsat_eval_check(ffsat_plan *plan, const float *x, float *F, float *grad,
                               float *con_val, int32_t *n_sat, uint32_t *unsat_bits, int32_t *U,
                               void *stream);
+/* One projected-gradient iteration with the check of its starting point,
+ * in one pass: at x_t (device [n][B], updated in place) computes F[b]
+ * (optional), the exact check outputs n_sat / U (optional, as in
+ * ffsat_round_check, for x_t), and x_{t+1} = clip(x_t - eta grad, -1, 1)
+ * with the gradient rounded to FP32 exactly as ffsat_eval returns it; the
+ * gradient itself is not stored. */
+ffsat_status ffsat_eval_step(ffsat_plan *plan, float *x, float eta, float *F, int32_t *n_sat,
+                             int32_t *U, void *stream);
 /* Same as ffsat_eval with double buffers and FP64 computation throughout. */
 ffsat_status ffsat_eval_f64(ffsat_plan *plan, const double *x, double *F, double *grad,
                             double *con_val, void *stream);
@@ -224,6 +232,24 @@ ffsat_status ffsat_erwa_update(ffsat_plan *plan, const int32_t *U, float alpha, 
  * with respect to w_c (F is linear in w, Def. 3).  Device buffers. */
 ffsat_status ffsat_weight_grad(ffsat_plan *plan, const float *con_val, const float *gF,
                                float *gw, void *stream);
+
+/* ---- differentiation of the objective (Def. 3) --------------------------- */
+
+/* Vector-Jacobian product of F (per restart) for an upstream gradient gF[B]:
+ *   gx[v*B+b] = gF[b] * grad[v*B+b]     (grad from ffsat_eval; optional)
+ *   gw[c]     = sum_b gF[b] * con_val[c*B+b]   (con_val from ffsat_eval; optional)
+ * Device buffers; gx may alias grad. */
+ffsat_status ffsat_vjp(ffsat_plan *plan, const float *grad, const float *con_val, const float *gF,
+                       float *gx, float *gw, void *stream);
+
+/* ---- restarts (App. "Restart Heuristics", rephasing) --------------------- */
+
+/* For every restart b with mask[b] != 0 (mask: device [B] int32, or NULL for
+ * all): mode 0 keeps x (original phase), 1 sets x <- -x (flipped phase),
+ * 2 draws x uniformly in [-1, 1) (random phase) from SplitMix64 applied to
+ * seed + (i+1) * 0x9e3779b97f4a7c15 for element i = v*B + b. */
+ffsat_status ffsat_rephase(ffsat_plan *plan, float *x, int32_t mode, uint64_t seed,
+                           const int32_t *mask, void *stream);
 
 /* ---- host-only helper ---------------------------------------------------- */
 

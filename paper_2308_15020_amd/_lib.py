@@ -71,6 +71,7 @@ _SIGS = {
     "ffsat_eval": (I32, [P, P, P, P, P, P]),
     "ffsat_eval_f64": (I32, [P, P, P, P, P, P]),
     "ffsat_eval_check": (I32, [P, P, P, P, P, P, P, P, P]),
+    "ffsat_eval_step": (I32, [P, P, C.c_float, P, P, P, P]),
     "ffsat_step": (I32, [P, P, P, P, C.c_float, P]),
     "ffsat_step_f64": (I32, [P, P, P, P, C.c_double, P]),
     "ffsat_run_steps": (I32, [P, P, I32, C.c_float, P, P]),
@@ -79,6 +80,8 @@ _SIGS = {
     "ffsat_erwa_update": (I32, [P, P, C.c_float, P]),
     "ffsat_weight_grad": (I32, [P, P, P, P, P]),
     "ffsat_coefficients": (I32, [I32, I32, I32, P]),
+    "ffsat_vjp": (I32, [P, P, P, P, P, P, P]),
+    "ffsat_rephase": (I32, [P, P, I32, C.c_uint64, P, P]),
     "ffsat_plan_profile": (I32, [P, I32]),
     "ffsat_plan_profile_read": (I32, [P, I32, C.c_char_p, C.c_size_t]),
 }

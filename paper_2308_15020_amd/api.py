@@ -174,6 +174,20 @@ class Plan:
         check(fn(self.handle, _ptr(x), _ptr(grad), _ptr(eta_b), float(eta), _stream(self.device)))
         return x
 
+    def eval_step(self, x: torch.Tensor, eta: float, want_F=True, want_check=True) -> dict:
+        """One fused iteration: F, n_sat and U at x_t, then x <- clip(x - eta grad, -1, 1)."""
+        self._x(x)
+        dev = self.device
+        out = {}
+        if want_F:
+            out["F"] = torch.empty(self.B, dtype=torch.float32, device=dev)
+        if want_check:
+            out["n_sat"] = torch.empty(self.B, dtype=torch.int32, device=dev)
+            out["U"] = torch.empty(self.m, dtype=torch.int32, device=dev)
+        check(lib().ffsat_eval_step(self.handle, _ptr(x), float(eta), _ptr(out.get("F")), _ptr(out.get("n_sat")),
+                                    _ptr(out.get("U")), _stream(dev)))
+        return out
+
     def run_steps(self, x: torch.Tensor, T: int, eta: float, F_last: Optional[torch.Tensor] = None):
         """T fused (gradient, projected step) iterations on x in place."""
         self._x(x)
@@ -211,6 +225,24 @@ class Plan:
         gw = torch.empty(self.m, dtype=torch.float32, device=self.device)
         check(lib().ffsat_weight_grad(self.handle, _ptr(con_val), _ptr(gF), _ptr(gw), _stream(self.device)))
         return gw
+
+    def vjp(self, gF: torch.Tensor, grad: Optional[torch.Tensor] = None,
+            con_val: Optional[torch.Tensor] = None) -> tuple:
+        """(gx, gw) for an upstream gradient gF[B] of F (either may be None)."""
+        dev = self.device
+        _need(gF, (self.B,), torch.float32, dev, "gF")
+        gx = torch.empty(self.n, self.B, dtype=torch.float32, device=dev) if grad is not None else None
+        gw = torch.empty(self.m, dtype=torch.float32, device=dev) if con_val is not None else None
+        check(lib().ffsat_vjp(self.handle, _ptr(grad), _ptr(con_val), _ptr(gF), _ptr(gx), _ptr(gw), _stream(dev)))
+        return gx, gw
+
+    def rephase(self, x: torch.Tensor, mode: int, seed: int = 0, mask: Optional[torch.Tensor] = None) -> None:
+        """0: keep, 1: flip, 2: redraw uniformly (restarts with mask[b] != 0, or all)."""
+        self._x(x)
+        if mask is not None:
+            _need(mask, (self.B,), torch.int32, self.device, "mask")
+        check(lib().ffsat_rephase(self.handle, _ptr(x), int(mode), int(seed) & ((1 << 64) - 1), _ptr(mask),
+                                  _stream(self.device)))
 
     def tune(self) -> None:
         check(lib().ffsat_plan_tune(self.handle, _stream(self.device)))

@@ -6,6 +6,8 @@
 //  * projected step; rounding of the variables (Alg. 1); adaptive weights
 //    (Prop. 3); weight gradient; small utilities.  The exact constraint
 //    check runs inside the evaluation kernels.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ffsat {
@@ -31,15 +33,12 @@ __global__ __launch_bounds__(RED_BLOCK) void k_reduce(ReduceArgs<IO> a, int n_gr
         double acc = 0.0;
         int e = e0;
         // independent loads first, then the additions in slot order
-        for (; e + 4 <= e1; e += 4) {
-            const IO s0 = a.slot[(size_t)a.vslot[e] * B + b];
-            const IO s1 = a.slot[(size_t)a.vslot[e + 1] * B + b];
-            const IO s2 = a.slot[(size_t)a.vslot[e + 2] * B + b];
-            const IO s3 = a.slot[(size_t)a.vslot[e + 3] * B + b];
-            acc += (double)s0;
-            acc += (double)s1;
-            acc += (double)s2;
-            acc += (double)s3;
+        for (; e + 8 <= e1; e += 8) {
+            IO sv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) sv[q] = a.slot[(size_t)a.vslot[e + q] * B + b];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc += (double)sv[q];
         }
         for (; e < e1; ++e) acc += (double)a.slot[(size_t)a.vslot[e] * B + b];
         const size_t idx = (size_t)v * B + b;
@@ -213,21 +212,22 @@ hipError_t launch_assign_bits_f64(int n, int B, const double *x, uint32_t *bits,
 
 // ---------------------------------------------------------------- adaptive weights
 
-__global__ __launch_bounds__(1024) void k_erwa(int m, const int32_t *__restrict__ U, float *w,
-                                               float alpha)
+// Every block finds max_c U_c itself (a grid-wide maximum without a second
+// launch or atomics), then updates its grid-stride share of the weights.
+__global__ __launch_bounds__(256) void k_erwa(int m, const int32_t *__restrict__ U, float *w, float alpha)
 {
-    __shared__ int32_t red[1024];
+    __shared__ int32_t red[256];
     int32_t mx = 0;
-    for (int c = threadIdx.x; c < m; c += blockDim.x) mx = max(mx, U[c]);
+    for (int c = threadIdx.x; c < m; c += 256) mx = max(mx, U[c]);
     red[threadIdx.x] = mx;
     __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    for (int h = 128; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + h]);
         __syncthreads();
     }
     const int32_t umax = red[0];
     const float inv = umax > 0 ? 1.0f / (float)umax : 0.0f;
-    for (int c = threadIdx.x; c < m; c += blockDim.x) {
+    for (int c = blockIdx.x * 256 + threadIdx.x; c < m; c += gridDim.x * 256) {
         const float r = umax > 0 ? (float)U[c] * inv : 0.0f;
         w[c] = (1.0f - alpha) * w[c] + alpha * r;
     }
@@ -235,7 +235,8 @@ __global__ __launch_bounds__(1024) void k_erwa(int m, const int32_t *__restrict_
 
 hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_erwa, dim3(1), dim3(1024), 0, s, m, U, w, alpha);
+    const int blocks = std::max(1, std::min((m + 1023) / 1024, 128));
+    hipLaunchKernelGGL(k_erwa, dim3(blocks), dim3(256), 0, s, m, U, w, alpha);
     return hipGetLastError();
 }
 
@@ -259,6 +260,61 @@ hipError_t launch_wgrad(int m, int B, const float *con_val, const float *gF, flo
 {
     hipLaunchKernelGGL(k_wgrad, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, m, B, con_val, gF,
                        gw);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- vector-Jacobian product
+
+// gx[v][b] = gF[b] * grad[v][b]: the gradient of sum_b gF_b F_b with respect to x
+__global__ void k_scale_restarts(int64_t total, int B, const float *__restrict__ grad, const float *__restrict__ gF,
+                                 float *gx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    gx[i] = gF[i % B] * grad[i];
+}
+
+hipError_t launch_scale_restarts(int64_t total, int B, const float *grad, const float *gF, float *gx, hipStream_t s)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_restarts, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total, B, grad, gF,
+                       gx);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- restarts
+
+// SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): the output function applied to seed + (i+1) *
+// golden gamma; the top 24 bits give a uniform float in [-1, 1).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Rephasing of selected restarts (App. Restart Heuristics): mode 0 keeps x
+// (original phase), 1 flips it (x <- -x), 2 redraws it uniformly in [-1, 1].
+// mask[b] != 0 selects restart b (mask may be null: all restarts).
+__global__ void k_rephase(int64_t total, int B, float *x, int mode, uint64_t seed, const int32_t *__restrict__ mask)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    if (mask != nullptr && mask[i % B] == 0) return;
+    if (mode == 1) {
+        x[i] = -x[i];
+    } else if (mode == 2) {
+        const uint64_t r = splitmix64(seed + (uint64_t)(i + 1) * 0x9e3779b97f4a7c15ull);
+        x[i] = (float)(r >> 40) * (2.0f / 16777216.0f) - 1.0f;
+    }
+}
+
+hipError_t launch_rephase(int64_t total, int B, float *x, int mode, uint64_t seed, const int32_t *mask, hipStream_t s)
+{
+    if (total <= 0 || mode == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rephase, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total, B, x, mode, seed,
+                       mask);
     return hipGetLastError();
 }
 

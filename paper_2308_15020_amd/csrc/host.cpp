@@ -418,6 +418,9 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
     }
     Ly.bins = sorted;
 
+    Ly.cost_prefix.assign((size_t)m + 1, 0.0);
+    for (int q = 0; q < m; ++q) Ly.cost_prefix[(size_t)q + 1] = Ly.cost_prefix[(size_t)q] + items[(size_t)q].cost;
+
     // 3. binned descriptors and literals, original -> binned positions
     std::vector<ConDesc> con((size_t)m);
     std::vector<int32_t> lit((size_t)p->nnz);
@@ -759,6 +762,49 @@ static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream
     return hipSuccess;
 }
 
+// Splits every bin heavier than an eighth of the total work into
+// cost-balanced contiguous constraint ranges, so that the streams can share
+// the work of one heavy bin.
+static std::vector<Bin> split_bins(const std::vector<Bin> &in, const std::vector<double> &pre)
+{
+    double total = 0;
+    for (const Bin &b : in) total += b.cost;
+    const double target = total / 8.0;
+    std::vector<Bin> out;
+    for (const Bin &b : in) {
+        const int parts = (int)std::min<double>(b.count, std::ceil(b.cost / std::max(target, 1e-30)));
+        if (parts <= 1) {
+            out.push_back(b);
+            continue;
+        }
+        const double c0 = pre[(size_t)b.first], c1 = pre[(size_t)b.first + b.count];
+        int start = b.first;
+        for (int q = 1; q <= parts; ++q) {
+            int end = b.first + b.count;
+            if (q < parts) {
+                const double goal = c0 + (c1 - c0) * q / parts;
+                end = (int)(std::lower_bound(pre.begin() + start + 1, pre.begin() + b.first + b.count, goal) - pre.begin());
+                end = std::max(end, start + 1);
+            }
+            if (end <= start) continue;
+            Bin part = b;
+            part.first = start;
+            part.count = end - start;
+            const double frac = (pre[(size_t)end] - pre[(size_t)start]) / std::max(c1 - c0, 1e-30);
+            part.cost = b.cost * frac;
+            part.flops = b.flops * frac;
+            part.bytes = b.bytes * frac;
+            part.exec_pos = b.exec_pos * frac;
+            part.lits = (int64_t)((double)b.lits * frac);
+            out.push_back(part);
+            start = end;
+            if (start >= b.first + b.count) break;
+        }
+    }
+    std::stable_sort(out.begin(), out.end(), [](const Bin &a, const Bin &b) { return a.cost > b.cost; });
+    return out;
+}
+
 // Constraints per wave: enough waves per bin to cover the chip (the
 // autotuner refines this).  Root-of-unity bins keep one constraint per wave.
 static void default_shapes(ffsat_plan *pl)
@@ -863,8 +909,8 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
     ffsat_plan *pl = new ffsat_plan();
     pl->p = p;
     pl->B = B;
-    pl->bins[0] = p->lay[0].bins;
-    pl->bins[1] = p->lay[1].bins;
+    pl->bins[0] = split_bins(p->lay[0].bins, p->lay[0].cost_prefix);
+    pl->bins[1] = split_bins(p->lay[1].bins, p->lay[1].cost_prefix);
     default_shapes(pl);
     pl->use_graphs = opts ? opts->use_graphs != 0 : true;
     if (opts && opts->tune_cache) pl->tune_cache = opts->tune_cache;
@@ -1078,6 +1124,17 @@ extern "C" ffsat_status ffsat_eval_check(ffsat_plan *pl, const float *x, float *
     return run_eval<float>(pl, x, F, grad, con_val, n_sat, unsat_bits, U, value, nullptr, 0.f, s);
 }
 
+extern "C" ffsat_status ffsat_eval_step(ffsat_plan *pl, float *x, float eta, float *F, int32_t *n_sat, int32_t *U,
+                                        void *stream)
+{
+    if (!pl || !x) return fail(FFSAT_E_INVALID_ARG, "NULL plan or x");
+    hipStream_t s = (hipStream_t)stream;
+    ffsat_status st = ensure_workspace(pl, IO_F32);
+    if (st != FFSAT_OK) return st;
+    if ((st = check_finite<float>(pl, x, s)) != FFSAT_OK) return st;
+    return run_eval<float>(pl, x, F, nullptr, nullptr, n_sat, nullptr, U, true, x, eta, s);
+}
+
 extern "C" ffsat_status ffsat_eval_f64(ffsat_plan *pl, const double *x, double *F, double *grad, double *con_val,
                                        void *stream)
 {
@@ -1196,5 +1253,32 @@ extern "C" ffsat_status ffsat_weight_grad(ffsat_plan *pl, const float *con_val, 
 {
     if (!pl || !con_val || !gF || !gw) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
     HIPCHK(launch_wgrad(pl->p->m, pl->B, con_val, gF, gw, (hipStream_t)stream));
+    return FFSAT_OK;
+}
+
+// ------------------------------------------------------------------ autograd, restarts
+
+extern "C" ffsat_status ffsat_vjp(ffsat_plan *pl, const float *grad, const float *con_val, const float *gF, float *gx,
+                                  float *gw, void *stream)
+{
+    if (!pl || !gF) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (gx) {
+        if (!grad) return fail(FFSAT_E_INVALID_ARG, "gx needs grad");
+        HIPCHK(launch_scale_restarts((int64_t)pl->p->n * pl->B, pl->B, grad, gF, gx, s));
+    }
+    if (gw) {
+        if (!con_val) return fail(FFSAT_E_INVALID_ARG, "gw needs con_val");
+        HIPCHK(launch_wgrad(pl->p->m, pl->B, con_val, gF, gw, s));
+    }
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_rephase(ffsat_plan *pl, float *x, int32_t mode, uint64_t seed, const int32_t *mask,
+                                      void *stream)
+{
+    if (!pl || !x) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    if (mode < 0 || mode > 2) return fail(FFSAT_E_INVALID_ARG, "mode must be 0 (original), 1 (flipped) or 2 (random)");
+    HIPCHK(launch_rephase((int64_t)pl->p->n * pl->B, pl->B, x, mode, seed, mask, (hipStream_t)stream));
     return FFSAT_OK;
 }

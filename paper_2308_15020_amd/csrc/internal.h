@@ -72,6 +72,7 @@ struct ProfRec {
 struct Layout {
     int io = IO_F32;
     std::vector<Bin> bins;
+    std::vector<double> cost_prefix;   // [m+1] prefix sums of per-constraint cost (binned order)
     ConDesc *d_con = nullptr;
     int32_t *d_lit = nullptr;    // var | (negated << 31), binned order
     int32_t *d_vptr = nullptr;   // [n+1] variable -> slot CSR
@@ -203,6 +204,10 @@ hipError_t launch_assign_bits_f64(int n, int B, const double *x, uint32_t *bits,
 hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, hipStream_t s);
 hipError_t launch_wgrad(int m, int B, const float *con_val, const float *gF, float *gw,
                         hipStream_t s);
+hipError_t launch_scale_restarts(int64_t total, int B, const float *grad, const float *gF, float *gx,
+                                 hipStream_t s);
+hipError_t launch_rephase(int64_t total, int B, float *x, int mode, uint64_t seed, const int32_t *mask,
+                          hipStream_t s);
 hipError_t launch_nonfinite_f32(int64_t total, const float *x, int32_t *flag, hipStream_t s);
 hipError_t launch_nonfinite_f64(int64_t total, const double *x, int32_t *flag, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);

@@ -1,0 +1,126 @@
+"""Autograd wrapper, restart kernels and the solve loop on the GPU.
+
+* the weighted objective on the mixed n = 2000 instance with w ~ U[0.5, 1.5],
+  x [2000][1024]: gradients with respect to x and w against the oracle's
+  analytic gradients and FP64 central differences (h = 1e-6);
+* rephasing (original / flipped / random with SplitMix64) bit-exact;
+* Alg. 1 on planted satisfiable instances: the returned assignment passes
+  the oracle's exact checker.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_cases import TOL32, var_scale
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ffs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2308_15020_amd as P
+    P.lib()
+    return P
+
+
+def test_autograd_weighted_objective(ffs):
+    from paper_2308_15020_amd.autograd import objective
+    inst = workloads.config4(workloads.instance_seed(4, 0))
+    B = 1024
+    prob = ffs.Problem(inst, device=0)
+    plan = ffs.Plan(prob, B)
+    xn = workloads.points(inst.n_vars, B, workloads.point_seed(4000))
+    x = torch.from_numpy(xn).to(DEV).requires_grad_(True)
+    w = torch.from_numpy(inst.weights.copy()).to(DEV).requires_grad_(True)
+    gF = torch.from_numpy(np.random.default_rng(3).normal(size=B).astype(np.float32)).to(DEV)
+    F = objective(x, w, plan)
+    (F * gF).sum().backward()
+    gx = x.grad.cpu().numpy()
+    gw = w.grad.cpu().numpy()
+    gFn = gF.cpu().numpy().astype(np.float64)
+    # analytic, on a restart subset (oracle cost)
+    cols = np.array([0, 5, 511, 1023])
+    sub = np.ascontiguousarray(xn[:, cols].astype(np.float64))
+    ref = oracle.eval_batch(inst, sub, w=inst.weights.astype(np.float64), want_con=True)
+    S = var_scale(inst)[:, None]
+    err_x = np.max(np.abs(gx[:, cols] - ref["g"] * gFn[cols]) / (S * np.abs(gFn[cols])))
+    assert err_x <= TOL32, err_x
+    # gw needs all restarts: sum_b gF_b WE_c(x_b), natural scale sum_b |gF_b|
+    full = oracle.eval_batch(inst, xn.astype(np.float64), w=inst.weights.astype(np.float64),
+                             want_g=False, want_con=True)
+    gw_ref = oracle.wgrad(full["con_val"], gFn)
+    err_w = np.max(np.abs(gw - gw_ref)) / np.abs(gFn).sum()
+    assert err_w <= TOL32, err_w
+    # FP64 central differences: 64 variables x 16 restarts, 64 weights
+    rng = np.random.default_rng(9)
+    sv = rng.integers(0, inst.n_vars, 64)
+    sb = rng.integers(0, B, 16)
+    vv, bb = np.meshgrid(sv, sb, indexing="ij")
+    fd = oracle.fd_grad(inst, xn.astype(np.float64), vv.ravel(), bb.ravel(),
+                        w=inst.weights.astype(np.float64), h=1e-6)
+    got = gx[vv.ravel(), bb.ravel()] / gFn[bb.ravel()]
+    scale = var_scale(inst)[vv.ravel()]
+    assert np.max(np.abs(got - fd) / scale) <= 1e-5
+    cs = rng.integers(0, inst.m, 64)
+    for c in cs:
+        e = np.zeros(inst.m)
+        e[c] = 1e-6
+        Fp = oracle.eval_batch(inst, xn.astype(np.float64)[:, :64], w=inst.weights + e, want_g=False)["F"]
+        Fm = oracle.eval_batch(inst, xn.astype(np.float64)[:, :64], w=inst.weights - e, want_g=False)["F"]
+        fdw = gFn[:64] @ (Fp - Fm) / 2e-6
+        # the GPU weight gradient restricted to the first 64 restarts
+        gw64 = float(gFn[:64] @ full["con_val"][c, :64])
+        assert abs(fdw - gw64) <= 1e-6 * np.abs(gFn[:64]).sum()
+
+
+def _splitmix64(z):
+    m = (1 << 64) - 1
+    z &= m
+    z = ((z ^ (z >> 30)) * 0xbf58476d1ce4e5b9) & m
+    z = ((z ^ (z >> 27)) * 0x94d049bb133111eb) & m
+    return z ^ (z >> 31)
+
+
+def test_rephase_modes(ffs):
+    inst = workloads.random_hybrid(37, 2, n_or=20, or_len=(2, 4))
+    B = 67
+    prob = ffs.Problem(inst, device=0)
+    plan = ffs.Plan(prob, B)
+    x0 = workloads.points(37, B, 5)
+    x = torch.from_numpy(x0).to(DEV)
+    plan.rephase(x, 0)
+    assert np.array_equal(x.cpu().numpy(), x0)
+    plan.rephase(x, 1)
+    assert np.array_equal(x.cpu().numpy(), -x0)
+    mask = torch.zeros(B, dtype=torch.int32, device=DEV)
+    mask[::3] = 1
+    seed = 123456789
+    plan.rephase(x, 2, seed=seed, mask=mask)
+    got = x.cpu().numpy()
+    idx = np.arange(37 * B).reshape(37, B)
+    want = -x0.copy()
+    for v in range(37):
+        for b in range(0, B, 3):
+            r = _splitmix64(seed + (int(idx[v, b]) + 1) * 0x9e3779b97f4a7c15)
+            want[v, b] = np.float32((r >> 40) * (2.0 / 16777216.0) - 1.0)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("policy,weighting", [("ROF", True), ("O", True), ("R", False)])
+def test_solver_planted(ffs, policy, weighting):
+    from paper_2308_15020_amd.solver import solve
+    inst, hidden = workloads.planted_hybrid(300, 11, n_or=1000, or_len=(3, 4), n_xor=10, xor_len=(2, 3),
+                                            n_card=10, card_len=(5, 20))
+    prob = ffs.Problem(inst, device=0)
+    res = solve(prob, B=256, rounds=60, T=40, eta=0.1, policy=policy, weighting=weighting, seed=7)
+    print(policy, weighting, res.solved, res.rounds, res.best_sat, inst.m, f"{res.seconds:.3f}s")
+    if policy == "ROF":
+        assert res.solved
+    if res.solved:
+        x = np.where(res.assignment, -1.0, 1.0)[:, None]
+        assert int(oracle.check(inst, x)["n_sat"][0]) == inst.m

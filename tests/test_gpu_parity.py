@@ -236,6 +236,22 @@ def test_run_steps_graph_equals_eager_loop(ffs, mixed):
     assert np.max(np.abs(res[0][1] - Flast)) <= 1e-6 * np.abs(inst.weights).sum()
 
 
+def test_eval_step_equals_eval_then_step(ffs, mixed):
+    inst, prob = mixed
+    B = 75
+    plan = ffs.Plan(prob, B)
+    x0 = points(inst, B, 61, "uniform")
+    xa = torch.from_numpy(x0).to(DEV)
+    xb = torch.from_numpy(x0).to(DEV)
+    for _ in range(3):
+        fused = to_np(plan.eval_step(xa, 0.07))
+        ref = to_np(plan.eval(xb, want_check=True))
+        plan.step(xb, torch.from_numpy(ref["grad"]).to(DEV), 0.07)
+        assert np.array_equal(fused["F"], ref["F"]) and np.array_equal(fused["n_sat"], ref["n_sat"])
+        assert np.array_equal(fused["U"], ref["U"])
+        assert np.array_equal(xa.cpu().numpy(), xb.cpu().numpy())
+
+
 def test_autotune_keeps_results(ffs, mixed, tmp_path):
     inst, prob = mixed
     B = 130

@@ -276,3 +276,47 @@ def points(n: int, B: int, seed: int, dist: str = "uniform",
     else:
         raise ValueError(dist)
     return np.ascontiguousarray(x.astype(dtype))
+
+
+def planted_hybrid(n: int, seed: int, *, n_or=0, or_len=(3, 3), n_xor=0, xor_len=(3, 3),
+                   n_card=0, card_len=(10, 10), name="") -> tuple:
+    """A hybrid formula satisfied by a hidden assignment (returned with it).
+
+    OR clauses with Bernoulli(1/2) signs are redrawn until the hidden
+    assignment satisfies them; XOR constraints take the parity of the hidden
+    assignment; at-least-t constraints take the all-positive or all-negative
+    sign that the hidden assignment makes more often true, and t ~ U{1..that
+    count} (so they hold).  Returns (Instance, hidden bool[n], True = True)."""
+    rng = np.random.default_rng(seed)
+    hidden = rng.random(n) < 0.5
+    groups = []
+
+    def lit_true(lits):
+        v = np.abs(lits) - 1
+        return np.where(lits > 0, hidden[v], ~hidden[v])
+
+    if n_or:
+        _, rows = _draw_group(rng, n, n_or, or_len[0], or_len[1], "bernoulli")
+        for i, r in enumerate(rows):
+            while not lit_true(r).any():
+                r = np.where(rng.random(r.size) < 0.5, -np.abs(r), np.abs(r)).astype(np.int32)
+            rows[i] = r
+        groups.append((KIND_OR, np.zeros(n_or, np.int32), rows))
+    if n_xor:
+        _, rows = _draw_group(rng, n, n_xor, xor_len[0], xor_len[1], "positive")
+        par = np.array([int(lit_true(r).sum() % 2) for r in rows])
+        groups.append((KIND_XOR, par, rows))
+    if n_card:
+        lens, rows = _draw_group(rng, n, n_card, card_len[0], card_len[1], "positive")
+        ts = []
+        for i, r in enumerate(rows):
+            pos = int(lit_true(np.abs(r)).sum())
+            neg = r.size - pos
+            if neg > pos:
+                rows[i] = (-np.abs(r)).astype(np.int32)
+                cnt = neg
+            else:
+                cnt = pos
+            ts.append(int(rng.integers(1, max(1, cnt) + 1)))
+        groups.append((KIND_CARD, np.array(ts), rows))
+    return assemble(n, groups, name=name or f"planted-n{n}"), hidden
