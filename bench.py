@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eta", type=float, default=0.05)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -117,6 +119,15 @@ def main():
         # x_{t+1} in one pass, then the adaptive weights from the check
         check(L.ffsat_eval_step(ph, p(x), eta, p(out["F"]), p(n_sat), p(U), stream))
         check(L.ffsat_erwa_update(ph, p(U), C.c_float(0.4), stream))
+
+    if args.copy_mib > 0:
+        # a plain copy kernel of known size: reads and writes copy_mib MiB
+        src = torch.ones(args.copy_mib * 262144, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()

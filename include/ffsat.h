@@ -251,6 +251,61 @@ ffsat_status ffsat_vjp(ffsat_plan *plan, const float *grad, const float *con_val
 ffsat_status ffsat_rephase(ffsat_plan *plan, float *x, int32_t mode, uint64_t seed,
                            const int32_t *mask, void *stream);
 
+/* ---- learned initialiser (proposal of restart points) -------------------- */
+
+/* A message-passing network over the clause-variable incidence graph that
+ * proposes restart points (the paper notes that the initial point matters,
+ * Sec. "Restart Heuristics"; the network itself is an addition).  Features:
+ * 8 per variable [1, P/8, N/8, (P-N)/(P+N+1), 0...] with P/N its positive /
+ * negative occurrences, 8 per constraint [1, is_or, is_xor, is_card, k/64,
+ * thr, parity, 0] with thr = t/k (t clipped to [0, k+1]) for at-least-t,
+ * 1/k for OR, 0 for XOR.  Layers (W stored [K][H], row-major FP32):
+ *   hv = relu(fv Ev + ev), hc = relu(fc Ec + ec)
+ *   per round: hc = relu([hc, mean+ hv, mean- hv] Wc + bc)   (mean over the
+ *              constraint's positive / negative literals, divided by k)
+ *              hv = relu([hv, mean+ hc, mean- hc] Wv + bv)   (divided by the
+ *              variable's occurrence count)
+ *   mu_v = tanh(hv . wo + bo)
+ * Parameters, flat FP32 in the order Ev[8][H], ev[H], Ec[8][H], ec[H], then
+ * per round Wc[3H][H], bc[H], Wv[3H][H], bv[H], then wo[H], bo[1].  Matrix
+ * products round both operands to bfloat16 (nearest even) and accumulate
+ * in FP32 on the matrix cores; everything else is FP32.  Loss: mean over
+ * variables of (mu_v - target_v)^2. */
+typedef struct ffsat_mpnn ffsat_mpnn;
+typedef struct {
+    int32_t hidden;     /* H: multiple of 32 in [32, 256] */
+    int32_t rounds;     /* R in [1, 8] */
+    int32_t device;     /* must be the current device */
+    int32_t reserved;   /* 0 */
+    uint64_t seed;      /* Glorot-uniform weights and head from SplitMix64; zero biases */
+} ffsat_mpnn_desc;
+
+ffsat_status ffsat_mpnn_create(const ffsat_mpnn_desc *d, ffsat_mpnn **out);
+ffsat_status ffsat_mpnn_destroy(ffsat_mpnn *net);
+ffsat_status ffsat_mpnn_num_params(const ffsat_mpnn *net, int64_t *n);
+/* Copies the parameters (which = 0) or the last gradients (which = 1,
+ * read only) between the network and buf (num_params floats, host memory
+ * unless on_device).  to_net = 1 loads parameters and resets Adam's moments
+ * and step count.  Host copies complete before return. */
+ffsat_status ffsat_mpnn_params(ffsat_mpnn *net, float *buf, int32_t which, int32_t to_net,
+                               int32_t on_device, void *stream);
+/* mu[n_vars] (device, optional) = the network's output on the problem's
+ * graph (built on first use and kept with the problem). */
+ffsat_status ffsat_mpnn_forward(ffsat_mpnn *net, ffsat_problem *p, float *mu, void *stream);
+/* Forward, loss against target[n_vars] (device) into *loss (device float,
+ * optional) and the gradient of the loss with respect to every parameter
+ * (read with ffsat_mpnn_params which = 1).  Split sums run in a fixed order:
+ * results are deterministic. */
+ffsat_status ffsat_mpnn_backward(ffsat_mpnn *net, ffsat_problem *p, const float *target, float *loss,
+                                 void *stream);
+/* One Adam step (bias-corrected) with the last gradients. */
+ffsat_status ffsat_mpnn_adam(ffsat_mpnn *net, float lr, float beta1, float beta2, float eps, void *stream);
+/* Restart points x[v*B+b] (device): the first round(frac_learned * B)
+ * restarts get clip(mu_v + sigma*u, -1, 1), the rest u, with u uniform in
+ * [-1, 1) from SplitMix64 of seed + (i+1) * 0x9e3779b97f4a7c15, i = v*B+b. */
+ffsat_status ffsat_mpnn_propose(ffsat_plan *plan, const float *mu, float *x, float frac_learned,
+                                float sigma, uint64_t seed, void *stream);
+
 /* ---- host-only helper ---------------------------------------------------- */
 
 /* Conjugated coefficients of one symmetric constraint in the bounded

@@ -45,6 +45,11 @@ class ProblemInfo(C.Structure):
                 ("device", C.c_int32), ("device_bytes", C.c_int64)]
 
 
+class MpnnDesc(C.Structure):
+    _fields_ = [("hidden", C.c_int32), ("rounds", C.c_int32), ("device", C.c_int32),
+                ("reserved", C.c_int32), ("seed", C.c_uint64)]
+
+
 class PlanOpts(C.Structure):
     _fields_ = [("autotune", C.c_int32), ("use_graphs", C.c_int32), ("tune_cache", C.c_char_p),
                 ("reserved", C.c_int32 * 8)]
@@ -84,6 +89,14 @@ _SIGS = {
     "ffsat_rephase": (I32, [P, P, I32, C.c_uint64, P, P]),
     "ffsat_plan_profile": (I32, [P, I32]),
     "ffsat_plan_profile_read": (I32, [P, I32, C.c_char_p, C.c_size_t]),
+    "ffsat_mpnn_create": (I32, [P, P]),
+    "ffsat_mpnn_destroy": (I32, [P]),
+    "ffsat_mpnn_num_params": (I32, [P, P]),
+    "ffsat_mpnn_params": (I32, [P, P, I32, I32, I32, P]),
+    "ffsat_mpnn_forward": (I32, [P, P, P, P]),
+    "ffsat_mpnn_backward": (I32, [P, P, P, P, P]),
+    "ffsat_mpnn_adam": (I32, [P, C.c_float, C.c_float, C.c_float, C.c_float, P]),
+    "ffsat_mpnn_propose": (I32, [P, P, P, C.c_float, C.c_float, C.c_uint64, P]),
 }
 
 

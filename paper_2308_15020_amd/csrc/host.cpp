@@ -33,6 +33,8 @@ static ffsat_status fail(ffsat_status st, const char *fmt, ...)
     return st;
 }
 
+ffsat_status ffsat_fail_external(ffsat_status st, const char *msg) { return fail(st, "%s", msg); }
+
 #define HIPCHK(call)                                                                      \
     do {                                                                                  \
         hipError_t e_ = (call);                                                           \
@@ -483,9 +485,11 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
     return FFSAT_OK;
 }
 
+
 static void free_problem(ffsat_problem *p)
 {
     if (!p) return;
+    ffsat_free_mpnn_graph(p->mpnn_graph);
     free_layout(p->lay[0]);
     free_layout(p->lay[1]);
     (void)hipFree(p->d_w);
@@ -518,6 +522,10 @@ extern "C" ffsat_status ffsat_problem_create(const ffsat_problem_desc *d, ffsat_
     std::vector<float> w((size_t)p->m, 1.0f);
     if (d->weights) std::copy(d->weights, d->weights + p->m, w.begin());
     std::vector<int32_t> kinds(d->kinds, d->kinds + p->m), params(d->params, d->params + p->m);
+    p->h_con_ptr.assign(d->con_ptr, d->con_ptr + p->m + 1);
+    p->h_lits.assign(d->lits, d->lits + p->nnz);
+    p->h_kinds = kinds;
+    p->h_params = params;
     CoeffMemo memo;
     if ((st = upload(&p->d_w, w, p->device_bytes)) != FFSAT_OK ||
         (st = upload(&p->d_kind, kinds, p->device_bytes)) != FFSAT_OK ||

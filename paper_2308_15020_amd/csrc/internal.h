@@ -100,6 +100,10 @@ struct ffsat_problem {
     int32_t *d_param = nullptr;
     ffsat::Layout lay[2];
     int64_t device_bytes = 0;
+    // host copy of the constraint set (original order)
+    std::vector<int64_t> h_con_ptr;
+    std::vector<int32_t> h_lits, h_kinds, h_params;
+    void *mpnn_graph = nullptr;   // incidence graph of the learned initialiser, built on first use
 };
 
 namespace ffsat {
@@ -136,6 +140,12 @@ struct GraphKey {
 };
 
 }  // namespace ffsat
+
+// Records msg as the thread's last error and returns st (for sources other
+// than the one holding the problem / plan entry points).
+ffsat_status ffsat_fail_external(ffsat_status st, const char *msg);
+// Frees the learned initialiser's incidence graph kept with a problem.
+void ffsat_free_mpnn_graph(void *g);
 
 struct ffsat_plan {
     ffsat_problem *p = nullptr;
