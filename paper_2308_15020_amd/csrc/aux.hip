@@ -212,31 +212,82 @@ hipError_t launch_assign_bits_f64(int n, int B, const double *x, uint32_t *bits,
 
 // ---------------------------------------------------------------- adaptive weights
 
-// Every block finds max_c U_c itself (a grid-wide maximum without a second
-// launch or atomics), then updates its grid-stride share of the weights.
-__global__ __launch_bounds__(256) void k_erwa(int m, const int32_t *__restrict__ U, float *w, float alpha)
+// ERWA (Prop. 3): w_c <- (1 - alpha) w_c + alpha U_c / max_c' U_c'.
+// Up to ERWA_ONE_BLOCK constraints one 1024-thread block does the maximum
+// (eight loads in flight per thread, wave reductions) and the update;
+// beyond that, per-block partial maxima first, then every block of the
+// update reduces the (at most 1024) partials itself.
+constexpr int ERWA_ONE_BLOCK = 1 << 16;
+
+__device__ __forceinline__ int32_t block_max_1024(int32_t v, int32_t *red)
 {
-    __shared__ int32_t red[256];
-    int32_t mx = 0;
-    for (int c = threadIdx.x; c < m; c += 256) mx = max(mx, U[c]);
-    red[threadIdx.x] = mx;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) red[wave] = v;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + h]);
-        __syncthreads();
+    v = lane < (int)(blockDim.x >> 6) ? red[lane] : 0;
+#pragma unroll
+    for (int d = 8; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ int32_t strided_max(int m, const int32_t *__restrict__ U, int begin, int stride)
+{
+    int32_t mx = 0;
+    int c = begin;
+    for (; c + 7 * stride < m; c += 8 * stride) {
+        int32_t q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] = U[c + u * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mx = max(mx, q[u]);
     }
-    const int32_t umax = red[0];
+    for (; c < m; c += stride) mx = max(mx, U[c]);
+    return mx;
+}
+
+__global__ __launch_bounds__(1024) void k_erwa_one(int m, const int32_t *__restrict__ U, float *w, float alpha)
+{
+    __shared__ int32_t red[16];
+    const int32_t umax = block_max_1024(strided_max(m, U, threadIdx.x, 1024), red);
     const float inv = umax > 0 ? 1.0f / (float)umax : 0.0f;
-    for (int c = blockIdx.x * 256 + threadIdx.x; c < m; c += gridDim.x * 256) {
+    for (int c = threadIdx.x; c < m; c += 1024) {
         const float r = umax > 0 ? (float)U[c] * inv : 0.0f;
         w[c] = (1.0f - alpha) * w[c] + alpha * r;
     }
 }
 
-hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, hipStream_t s)
+__global__ __launch_bounds__(1024) void k_umax_part(int m, const int32_t *__restrict__ U, int32_t *part)
 {
-    const int blocks = std::max(1, std::min((m + 1023) / 1024, 128));
-    hipLaunchKernelGGL(k_erwa, dim3(blocks), dim3(256), 0, s, m, U, w, alpha);
+    __shared__ int32_t red[16];
+    const int32_t v = block_max_1024(strided_max(m, U, blockIdx.x * 1024 + threadIdx.x, gridDim.x * 1024), red);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(1024) void k_erwa_apply(int m, int nparts, const int32_t *__restrict__ part,
+                                                     const int32_t *__restrict__ U, float *w, float alpha)
+{
+    __shared__ int32_t red[16];
+    const int32_t umax = block_max_1024((int)threadIdx.x < nparts ? part[threadIdx.x] : 0, red);
+    const float inv = umax > 0 ? 1.0f / (float)umax : 0.0f;
+    for (int c = blockIdx.x * 1024 + threadIdx.x; c < m; c += gridDim.x * 1024) {
+        const float r = umax > 0 ? (float)U[c] * inv : 0.0f;
+        w[c] = (1.0f - alpha) * w[c] + alpha * r;
+    }
+}
+
+hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, int32_t *part, hipStream_t s)
+{
+    if (m <= ERWA_ONE_BLOCK) {
+        hipLaunchKernelGGL(k_erwa_one, dim3(1), dim3(1024), 0, s, m, U, w, alpha);
+        return hipGetLastError();
+    }
+    const int nparts = std::min(1024, (m + 8191) / 8192);
+    hipLaunchKernelGGL(k_umax_part, dim3(nparts), dim3(1024), 0, s, m, U, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_erwa_apply, dim3(nparts), dim3(1024), 0, s, m, nparts, part, U, w, alpha);
     return hipGetLastError();
 }
 

@@ -160,26 +160,82 @@ __device__ __forceinline__ int group_sum_int(int v)
     return v;
 }
 
-// Read-only inputs are separate __restrict__ arguments: the compiler may
-// then read uniform descriptors and coefficients through the scalar cache.
+// One complex frequency of a constraint: steps i-ii (affine factors psi and
+// their running product), step iii (value term Re(c0 * prod psi)) and the
+// reverse traversal that adds Re(c1 * leave-one-out product) to every
+// position's gradient.  FORM 1: psi = 1 - i tk l; FORM 2: psi = tk - i l.
+template <typename CT, int SEG, int L, int FORM>
+__device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (&gr)[SEG], const FreqT<CT> &fr,
+                                          CT &we)
+{
+    const CT tk = fr.tk;
+    CT pr[SEG], pi[SEG];
+    CT Pr = fr.init, Pi = 0;
+#pragma unroll
+    for (int t = 0; t < SEG; ++t) {
+        pr[t] = Pr; pi[t] = Pi;
+        if constexpr (FORM == 1) {
+            const CT u = tk * lv[t];
+            const CT nr = fmaT(Pi, u, Pr);
+            const CT ni = fmaT(-Pr, u, Pi);
+            Pr = nr; Pi = ni;
+        } else {
+            const CT l = lv[t];
+            const CT nr = fmaT(Pi, l, tk * Pr);
+            const CT ni = fmaT(-Pr, l, tk * Pi);
+            Pr = nr; Pi = ni;
+        }
+    }
+    CT er, ei, sr, si;
+    group_scan_cplx<CT, L>(j, Pr, Pi, er, ei, sr, si);
+    const CT Gr = fmaT(Pr, sr, -Pi * si);
+    const CT Gi = fmaT(Pr, si, Pi * sr);
+    we += fmaT(fr.c0re, Gr, -fr.c0im * Gi);
+    // the factors are recomputed from an opaque copy of tk so that the
+    // forward products are not kept alive across both passes
+    CT tkb = tk;
+    asm volatile("" : "+v"(tkb));
+    const CT qr = fmaT(er, sr, -ei * si);
+    const CT qi = fmaT(er, si, ei * sr);
+    CT Sr = fmaT(fr.c1re, qr, -fr.c1im * qi);
+    CT Si = fmaT(fr.c1re, qi, fr.c1im * qr);
+#pragma unroll
+    for (int t = SEG - 1; t >= 0; --t) {
+        gr[t] = fmaT(pr[t], Sr, fmaT(-pi[t], Si, gr[t]));
+        if (t > 0) {
+            if constexpr (FORM == 1) {
+                const CT u = tkb * lv[t];
+                const CT nr = fmaT(Si, u, Sr);
+                const CT ni = fmaT(-Sr, u, Si);
+                Sr = nr; Si = ni;
+            } else {
+                const CT l = lv[t];
+                const CT nr = fmaT(Si, l, tkb * Sr);
+                const CT ni = fmaT(-Sr, l, tkb * Si);
+                Sr = nr; Si = ni;
+            }
+        }
+    }
+}
+
+// The work of one wave: unit = (chunk of sp.cpw constraints of the range
+// sp.first .. sp.first + sp.count, restart block rb).  `unit` must be
+// wave-uniform.  Read-only inputs are separate __restrict__ arguments: the
+// compiler may then read uniform descriptors and coefficients through the
+// scalar cache.
 template <typename IO, typename CT, int SEG, int L, bool CPLX>
-__global__ __launch_bounds__(256) void k_eval(EvalArgs<IO> a, const IO *__restrict__ xin,
-                                              const ConDesc *__restrict__ con,
-                                              const int32_t *__restrict__ lits,
-                                              const float *__restrict__ wts,
-                                              const TypeT<CT> *__restrict__ types,
-                                              const FreqT<CT> *__restrict__ freqs)
+__device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, const int unit,
+                                          const IO *__restrict__ xin, const ConDesc *__restrict__ con,
+                                          const int32_t *__restrict__ lits, const float *__restrict__ wts,
+                                          const TypeT<CT> *__restrict__ types,
+                                          const FreqT<CT> *__restrict__ freqs)
 {
     constexpr int RPW = 64 / L;
     const int lane = threadIdx.x & 63;
-    // the wave index is uniform: say so, so that everything derived from it
-    // (constraint descriptors, coefficient tables, loop bounds) stays scalar
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int unit = blockIdx.x * (blockDim.x >> 6) + wave;
-    const int n_chunks = (a.count + a.cpw - 1) / a.cpw;
-    if (unit >= n_chunks * a.n_rb) return;   // whole wave leaves together
-    const int chunk = unit / a.n_rb;
-    const int rb = unit - chunk * a.n_rb;
+    const int n_chunks = (sp.count + sp.cpw - 1) / sp.cpw;
+    if (unit >= n_chunks * sp.n_rb) return;   // whole wave leaves together
+    const int chunk = unit / sp.n_rb;
+    const int rb = unit - chunk * sp.n_rb;
     const int j = lane & (L - 1);
     const int r = lane / L;
     const int b = rb * RPW + r;
@@ -188,11 +244,11 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<IO> a, const IO *__restri
     const int i0 = j * SEG;
     CT facc = 0;
     int nunsat = 0;
-    const int c_begin = chunk * a.cpw;
-    const int c_end = min(c_begin + a.cpw, a.count);
+    const int c_begin = chunk * sp.cpw;
+    const int c_end = min(c_begin + sp.cpw, sp.count);
 #pragma unroll 1
     for (int ci = c_begin; ci < c_end; ++ci) {
-        const ConDesc d = con[a.first + ci];
+        const ConDesc d = con[sp.first + ci];
         const TypeT<CT> ty = types[d.type];
         const int k = d.k;
 
@@ -200,25 +256,31 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<IO> a, const IO *__restri
         // positions past the constraint's end hold the padding value (count
         // neutral; its factor is divided out of the coefficients on the
         // host).  Also the rounded truth of each literal (x_v < 0: True).
+        // Branch-free: all literal loads (indices clamped into the
+        // constraint), then all point loads, so that a lane waits for two
+        // memory round trips per constraint rather than two per position.
+        int nv = min(max(k - i0, 0), SEG);   // positions of this lane inside the constraint
+        int lt[SEG];
+#pragma unroll
+        for (int t = 0; t < SEG; ++t) lt[t] = lits[d.off + min(i0 + t, k - 1)];
+        IO xr[SEG];
+#pragma unroll
+        for (int t = 0; t < SEG; ++t) xr[t] = xin[(size_t)(lt[t] & 0x7fffffff) * a.B + bb];
         CT lv[SEG];
         uint32_t negm = 0, tmask = 0;
 #pragma unroll
         for (int t = 0; t < SEG; ++t) {
-            CT val = ty.pad;
-            const int i = i0 + t;
-            if (i < k) {
-                const int lit = lits[d.off + i];
-                const int v = lit & 0x7fffffff;
-                const IO xr = xin[(size_t)v * a.B + bb];
-                const CT xv = (CT)xr;
-                const bool neg = lit < 0;
-                val = neg ? -xv : xv;
-                negm |= (neg ? 1u : 0u) << t;
-                const bool vt = xr < IO(0);
-                tmask |= ((neg ? !vt : vt) ? 1u : 0u) << t;
-            }
-            lv[t] = val;
+            const bool in = t < nv;
+            const bool neg = lt[t] < 0;
+            const CT xv = (CT)xr[t];
+            lv[t] = in ? (neg ? -xv : xv) : ty.pad;
+            const bool vt = xr[t] < IO(0);
+            negm |= ((in && neg) ? 1u : 0u) << t;
+            tmask |= ((in && (neg != vt)) ? 1u : 0u) << t;
         }
+        // opaque: otherwise the stores re-derive the sign bits from the
+        // loaded literals, which then stay live across the frequency loop
+        asm volatile("" : "+v"(negm));
         if (a.want_check) {
             const int cnt = group_sum_int<L>(__popc(tmask));
             const bool sat = d.chk >= 0 ? (cnt >= d.chk) : ((cnt & 1) == (d.chk == -2 ? 1 : 0));
@@ -235,76 +297,26 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<IO> a, const IO *__restri
 
         CT gr[SEG];
 #pragma unroll
-        for (int t = 0; t < SEG; ++t) gr[t] = 0;
+        for (int t = 0; t < SEG; ++t) {
+            gr[t] = 0;
+            // materialised here, once: keeps one register set for the
+            // accumulators across both frequency loops (no bypass copies)
+            if constexpr (CPLX) asm volatile("" : "+v"(gr[t]));
+        }
         CT we = 0;
         if constexpr (CPLX) {
-            const int nf = ty.n1 + ty.n2;
+            const int n1 = ty.n1, nf = ty.n1 + ty.n2;
             FreqT<CT> fr = freqs[ty.tab];
 #pragma unroll 1
-            for (int f = 0; f < nf; ++f) {
+            for (int f = 0; f < n1; ++f) {
                 const FreqT<CT> nxt = freqs[ty.tab + f + 1];   // table has one entry of padding
-                const bool form1 = f < ty.n1;
-                const CT tk = fr.tk;
-                CT pr[SEG], pi[SEG];
-                CT Pr = fr.init, Pi = 0;
-                // steps i-ii: affine factors and their running product
-                if (form1) {
-#pragma unroll
-                    for (int t = 0; t < SEG; ++t) {
-                        pr[t] = Pr; pi[t] = Pi;
-                        const CT u = tk * lv[t];
-                        const CT nr = fmaT(Pi, u, Pr);
-                        const CT ni = fmaT(-Pr, u, Pi);
-                        Pr = nr; Pi = ni;
-                    }
-                } else {
-#pragma unroll
-                    for (int t = 0; t < SEG; ++t) {
-                        pr[t] = Pr; pi[t] = Pi;
-                        const CT l = lv[t];
-                        const CT nr = fmaT(Pi, l, tk * Pr);
-                        const CT ni = fmaT(-Pr, l, tk * Pi);
-                        Pr = nr; Pi = ni;
-                    }
-                }
-                CT er, ei, sr, si;
-                group_scan_cplx<CT, L>(j, Pr, Pi, er, ei, sr, si);
-                // step iii (lane j == 0 holds the full product T0 * suffix)
-                const CT Gr = fmaT(Pr, sr, -Pi * si);
-                const CT Gi = fmaT(Pr, si, Pi * sr);
-                we += fmaT(fr.c0re, Gr, -fr.c0im * Gi);
-                // reverse traversal seeded with c1 * (other segments).  The
-                // factors are recomputed from an opaque copy of tk so that the
-                // forward products are not kept alive across both passes.
-                CT tkb = tk;
-                asm volatile("" : "+v"(tkb));
-                const CT qr = fmaT(er, sr, -ei * si);
-                const CT qi = fmaT(er, si, ei * sr);
-                CT Sr = fmaT(fr.c1re, qr, -fr.c1im * qi);
-                CT Si = fmaT(fr.c1re, qi, fr.c1im * qr);
-                if (form1) {
-#pragma unroll
-                    for (int t = SEG - 1; t >= 0; --t) {
-                        gr[t] = fmaT(pr[t], Sr, fmaT(-pi[t], Si, gr[t]));
-                        if (t > 0) {
-                            const CT u = tkb * lv[t];
-                            const CT nr = fmaT(Si, u, Sr);
-                            const CT ni = fmaT(-Sr, u, Si);
-                            Sr = nr; Si = ni;
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int t = SEG - 1; t >= 0; --t) {
-                        gr[t] = fmaT(pr[t], Sr, fmaT(-pi[t], Si, gr[t]));
-                        if (t > 0) {
-                            const CT l = lv[t];
-                            const CT nr = fmaT(Si, l, tkb * Sr);
-                            const CT ni = fmaT(-Sr, l, tkb * Si);
-                            Sr = nr; Si = ni;
-                        }
-                    }
-                }
+                freq_pass<CT, SEG, L, 1>(j, lv, gr, fr, we);
+                fr = nxt;
+            }
+#pragma unroll 1
+            for (int f = n1; f < nf; ++f) {
+                const FreqT<CT> nxt = freqs[ty.tab + f + 1];
+                freq_pass<CT, SEG, L, 2>(j, lv, gr, fr, we);
                 fr = nxt;
             }
         }
@@ -332,10 +344,13 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<IO> a, const IO *__restri
         if (j == 0) facc = fmaT(wc, we, facc);
         if (a.con_val != nullptr && j == 0 && bok) a.con_val[(size_t)d.orig * a.B + b] = (IO)we;
         if (a.want_grad && bok) {
+            // fresh predicates: keep the load phase's lane masks from living
+            // across the frequency loop
+            asm volatile("" : "+v"(nv));
 #pragma unroll
             for (int t = 0; t < SEG; ++t) {
                 const int i = i0 + t;
-                if (i < k) {
+                if (t < nv) {
                     const CT gv = ((negm >> t) & 1u) ? -gr[t] : gr[t];
                     a.slot[(size_t)(d.off + i) * a.B + b] = (IO)(wc * gv);
                 }
@@ -343,10 +358,27 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<IO> a, const IO *__restri
         }
     }
     if (j == 0 && bok) {
-        const size_t row = (size_t)(a.fpart_row0 + chunk) * a.B + b;
+        const size_t row = (size_t)(sp.fpart_row0 + chunk) * a.B + b;
         if (a.do_value) a.fpart[row] = (IO)facc;
         if (a.want_check) a.cpart[row] = nunsat;
     }
+}
+
+// One bin per launch.
+template <typename IO, typename CT, int SEG, int L, bool CPLX>
+__global__ __launch_bounds__(256) void k_eval(EvalArgs<IO> a, const IO *__restrict__ xin,
+                                              const ConDesc *__restrict__ con,
+                                              const int32_t *__restrict__ lits,
+                                              const float *__restrict__ wts,
+                                              const TypeT<CT> *__restrict__ types,
+                                              const FreqT<CT> *__restrict__ freqs)
+{
+    // the wave index is uniform: say so, so that everything derived from it
+    // (constraint descriptors, coefficient tables, loop bounds) stays scalar
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int unit = blockIdx.x * (blockDim.x >> 6) + wave;
+    const Span sp{a.first, a.count, a.cpw, a.n_rb, a.fpart_row0};
+    eval_unit<IO, CT, SEG, L, CPLX>(a, sp, unit, xin, con, lits, wts, types, freqs);
 }
 
 template <typename IO>

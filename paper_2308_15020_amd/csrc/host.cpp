@@ -925,6 +925,7 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
     ffsat_status st = ensure_workspace(pl, IO_F32);
     if (st == FFSAT_OK) {
         hipError_t e = hipMalloc(&pl->d_flag, sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&pl->d_umax, 1024 * sizeof(int32_t));
         if (e != hipSuccess) st = fail(FFSAT_E_NOMEM, "hipMalloc flag: %s", hipGetErrorString(e));
     }
     if (st == FFSAT_OK && !(opts && opts->reserved[0] == 1)) {
@@ -1004,6 +1005,7 @@ extern "C" ffsat_status ffsat_plan_destroy(ffsat_plan *pl)
         (void)hipFree(pl->d_ftmp[io]);
     }
     (void)hipFree(pl->d_flag);
+    (void)hipFree(pl->d_umax);
     (void)hipFree(pl->d_cpart);
     (void)hipFree(pl->d_ctmp);
     (void)hipFree(pl->d_scratch_x);
@@ -1252,7 +1254,7 @@ extern "C" ffsat_status ffsat_erwa_update(ffsat_plan *pl, const int32_t *U, floa
 {
     if (!pl || !U) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
     if (!(alpha >= 0.f && alpha <= 1.f)) return fail(FFSAT_E_INVALID_ARG, "alpha must be in [0, 1]");
-    HIPCHK(launch_erwa(pl->p->m, U, pl->p->d_w, alpha, (hipStream_t)stream));
+    HIPCHK(launch_erwa(pl->p->m, U, pl->p->d_w, alpha, pl->d_umax, (hipStream_t)stream));
     return FFSAT_OK;
 }
 

@@ -126,6 +126,11 @@ struct EvalArgs {
     int want_grad, do_value, want_check, wm;
 };
 
+// A wave's constraint range and tiling (one bin, or one entry of a grouped launch).
+struct Span {
+    int first, count, cpw, n_rb, fpart_row0;
+};
+
 struct GraphKey {
     const void *x;
     int32_t T;
@@ -158,6 +163,7 @@ struct ffsat_plan {
     int32_t *d_ctmp = nullptr;
     int fpart_rows[2] = {0, 0};
     int32_t *d_flag = nullptr;       // debug non-finite flag
+    int32_t *d_umax = nullptr;       // [1024] partial maxima of the weight update
     float *d_scratch_x = nullptr;    // autotuner input
     hipStream_t cap = nullptr;       // capture stream for graphs
     // three side streams: with the caller's stream, one per hardware queue
@@ -211,7 +217,7 @@ hipError_t launch_step_f64(int64_t total, int B, double *x, const double *g,
                            const double *eta_b, double eta, hipStream_t s);
 hipError_t launch_assign_bits_f32(int n, int B, const float *x, uint32_t *bits, hipStream_t s);
 hipError_t launch_assign_bits_f64(int n, int B, const double *x, uint32_t *bits, hipStream_t s);
-hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, hipStream_t s);
+hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, int32_t *part, hipStream_t s);
 hipError_t launch_wgrad(int m, int B, const float *con_val, const float *gF, float *gw,
                         hipStream_t s);
 hipError_t launch_scale_restarts(int64_t total, int B, const float *grad, const float *gF, float *gx,

@@ -1,0 +1,80 @@
+"""Summaries of rocprofv3 CSV output for the library's kernels.
+
+  python -m paper_2308_15020_amd.profsum trace <..._kernel_trace.csv>
+      per (kernel, grid) dispatch count, average / total duration, share
+  python -m paper_2308_15020_amd.profsum pmc <..._counter_collection.csv> [--copy-mib M]
+      per (kernel, grid) average of each counter per dispatch; with
+      --copy-mib, the same counters for the largest plain copy dispatch and
+      the factor (M MiB / counter) that turns FETCH_SIZE / WRITE_SIZE into
+      bytes
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import re
+from collections import defaultdict
+
+
+def short(name: str) -> str:
+    name = re.sub(r"\s+", " ", name)
+    m = re.search(r"(k_\w+)(<[^()]*>)?", name)
+    if m:
+        return m.group(1) + (m.group(2) or "")
+    return name[:200]
+
+
+def trace(path: str, top: int = 25) -> str:
+    acc = defaultdict(lambda: [0, 0.0])
+    for r in csv.DictReader(open(path)):
+        key = (short(r["Kernel_Name"]), r.get("Grid_Size_X", "?") + "x" + r.get("Grid_Size_Y", "?"))
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        acc[key][0] += 1
+        acc[key][1] += d
+    tot = sum(v[1] for v in acc.values())
+    lines = [f"{'kernel':<60} {'grid':>14} {'calls':>6} {'avg_us':>9} {'total_us':>10} {'share':>6}"]
+    for (k, g), (n, t) in sorted(acc.items(), key=lambda kv: -kv[1][1])[:top]:
+        lines.append(f"{k[:60]:<60} {g:>14} {n:>6} {t / n:>9.2f} {t:>10.1f} {t / tot:>6.3f}")
+    return "\n".join(lines)
+
+
+def pmc(path: str, copy_mib: float = 0.0, top: int = 25) -> str:
+    acc = defaultdict(lambda: defaultdict(float))
+    calls = defaultdict(set)
+    for r in csv.DictReader(open(path)):
+        key = (short(r["Kernel_Name"]), r.get("Grid_Size", r.get("Grid_Size_X", "?")))
+        acc[key][r["Counter_Name"]] += float(r["Counter_Value"])
+        calls[key].add(r["Dispatch_Id"])
+    names = sorted({c for v in acc.values() for c in v})
+    lines = [f"{'kernel':<60} {'grid':>10} {'calls':>6} " + " ".join(f"{c:>16}" for c in names)]
+    order = sorted(acc.items(), key=lambda kv: -max(kv[1].values()) / len(calls[kv[0]]))
+    for key, cv in order[:top]:
+        n = len(calls[key])
+        lines.append(f"{key[0][:60]:<60} {key[1]:>10} {n:>6} " + " ".join(f"{cv[c] / n:>16.1f}" for c in names))
+    if copy_mib > 0:
+        # FETCH_SIZE / WRITE_SIZE are in KiB: the plain elementwise kernel that
+        # reads and writes copy_mib MiB gives the scale of each counter
+        cands = [k for k in acc if "elementwise" in k[0].lower()]
+        lines.append("")
+        lines.append(f"calibration: plain elementwise kernel reading and writing {copy_mib:g} MiB")
+        for c in names:
+            best = max(cands, key=lambda k: acc[k][c] / len(calls[k]), default=None)
+            if best is None or acc[best][c] <= 0:
+                continue
+            per = acc[best][c] / len(calls[best])
+            lines.append(f"  {c}: {per:.1f} KiB per dispatch -> scale {copy_mib * 1024 / per:.4f}")
+    return "\n".join(lines)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("kind", choices=["trace", "pmc"])
+    ap.add_argument("csv")
+    ap.add_argument("--copy-mib", type=float, default=0.0)
+    ap.add_argument("--top", type=int, default=25)
+    a = ap.parse_args()
+    print(trace(a.csv, a.top) if a.kind == "trace" else pmc(a.csv, a.copy_mib, a.top))
+
+
+if __name__ == "__main__":
+    main()

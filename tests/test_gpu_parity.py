@@ -195,6 +195,24 @@ def test_weights_erwa_and_weight_gradient(ffs, mixed):
     assert np.array_equal(prob.get_weights().cpu().numpy(), inst.weights)
 
 
+def test_erwa_large_m_two_pass(ffs):
+    """More than 65536 constraints: partial maxima, then the update."""
+    rng = np.random.default_rng(17)
+    m, n = 70001, 500
+    lits = np.stack([rng.choice(n, 3, replace=False) + 1 for _ in range(64)])
+    lits = lits[rng.integers(0, 64, m)] * np.where(rng.random((m, 3)) < 0.5, -1, 1)
+    inst = workloads.assemble(n, [(0, np.zeros(m, np.int32), list(lits.astype(np.int32)))])
+    prob = ffs.Problem(inst, device=0)
+    plan = ffs.Plan(prob, 64)
+    w0 = rng.uniform(0.5, 1.5, m).astype(np.float32)
+    prob.set_weights(w0)
+    Un = rng.integers(0, 64, m).astype(np.int32)
+    Un[12345] = 977   # the maximum sits in one block's range
+    plan.erwa_update(torch.from_numpy(Un).to(DEV), 0.3)
+    want = oracle.erwa(Un, w0.astype(np.float64), 0.3)
+    assert np.max(np.abs(prob.get_weights().cpu().numpy() - want)) <= 1e-6
+
+
 def test_determinism(ffs, mixed):
     """Bitwise-equal results on repeated calls, with bins on side streams or
     all on one stream."""
