@@ -242,6 +242,23 @@ ffsat_status ffsat_weight_grad(ffsat_plan *plan, const float *con_val, const flo
 ffsat_status ffsat_vjp(ffsat_plan *plan, const float *grad, const float *con_val, const float *gF,
                        float *gx, float *gw, void *stream);
 
+/* ---- accelerated projected gradient (Alg. 5 and the line search it names) */
+
+/* T iterations of FISTA with backtracking for every restart b, on device
+ * state x[v*B+b], y[v*B+b] (the extrapolated point), eta[b] (step size),
+ * t[b] (momentum; start with y = x, t = 1, eta = the initial step):
+ *   restarts with eta < 1e-12 have stopped (Alg. 5) and are left unchanged;
+ *   g = gradient of F at y;
+ *   up to max_ls trials: z = clip(y - eta g, -1, 1); accept when
+ *     F(z) <= F(y) + <g, z - y> + |z - y|^2 / (2 eta), else eta /= 2
+ *     (after the last trial z is taken with the halved eta);
+ *   t' = (1 + sqrt(1 + 4 t^2)) / 2, y' = z + ((t - 1)/t') (z - x), x' = z.
+ * F (optional, [B]) receives F(x') of every restart that moved.  The search
+ * reads one counter back to the host per trial (synchronises the stream);
+ * the workspace (two [n][B] arrays) is allocated on first use. */
+ffsat_status ffsat_fista(ffsat_plan *plan, float *x, float *y, float *eta, float *t, int32_t T,
+                         int32_t max_ls, float *F, void *stream);
+
 /* ---- restarts (App. "Restart Heuristics", rephasing) --------------------- */
 
 /* For every restart b with mask[b] != 0 (mask: device [B] int32, or NULL for

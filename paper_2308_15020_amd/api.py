@@ -244,6 +244,24 @@ class Plan:
         check(lib().ffsat_rephase(self.handle, _ptr(x), int(mode), int(seed) & ((1 << 64) - 1), _ptr(mask),
                                   _stream(self.device)))
 
+    def fista_state(self, x: torch.Tensor, eta0: float) -> dict:
+        """Fresh FISTA state for the points x: y = x, eta = eta0, t = 1."""
+        self._x(x)
+        return {"y": x.clone(), "eta": torch.full((self.B,), float(eta0), dtype=torch.float32, device=self.device),
+                "t": torch.ones(self.B, dtype=torch.float32, device=self.device)}
+
+    def fista(self, x: torch.Tensor, state: dict, T: int, max_ls: int = 15,
+              F: Optional[torch.Tensor] = None) -> None:
+        """T FISTA iterations with backtracking (ffsat_fista), in place on x and state."""
+        self._x(x)
+        self._x(state["y"])
+        _need(state["eta"], (self.B,), torch.float32, self.device, "eta")
+        _need(state["t"], (self.B,), torch.float32, self.device, "t")
+        if F is not None:
+            _need(F, (self.B,), torch.float32, self.device, "F")
+        check(lib().ffsat_fista(self.handle, _ptr(x), _ptr(state["y"]), _ptr(state["eta"]), _ptr(state["t"]),
+                                int(T), int(max_ls), _ptr(F), _stream(self.device)))
+
     def tune(self) -> None:
         check(lib().ffsat_plan_tune(self.handle, _stream(self.device)))
 

@@ -411,3 +411,143 @@ hipError_t launch_scratch_points(float *x, int64_t total, uint32_t seed, hipStre
 }
 
 }  // namespace ffsat
+
+// ---------------------------------------------------------------- FISTA with backtracking
+// Per restart b (columns of [n][B] arrays): see ffsat_fista in ffsat.h.
+
+namespace ffsat {
+
+constexpr float FISTA_ETA_MIN = 1e-12f;
+
+__global__ void k_fista_begin(int B, const float *__restrict__ eta, int32_t *active, int32_t *searching)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const int32_t a = eta[b] >= FISTA_ETA_MIN ? 1 : 0;
+    active[b] = a;
+    searching[b] = a;
+}
+
+// z = clip(y - eta_b g) for the restarts still searching, and per (chunk of
+// `rows` variables, restart) partial sums of g.(z - y) and |z - y|^2
+__global__ __launch_bounds__(256) void k_fista_trial(int n, int B, int rows, int chunks, const float *__restrict__ y,
+                                                     const float *__restrict__ g, const float *__restrict__ eta,
+                                                     const int32_t *__restrict__ searching, float *z, float *part)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B || !searching[b]) return;
+    const float e = eta[b];
+    const int v0 = blockIdx.y * rows, v1 = min(n, v0 + rows);
+    float dot = 0.f, sq = 0.f;
+    for (int v = v0; v < v1; ++v) {
+        const size_t i = (size_t)v * B + b;
+        const float yv = y[i], gv = g[i];
+        const float zv = fminf(fmaxf(yv - e * gv, -1.f), 1.f);
+        z[i] = zv;
+        const float d = zv - yv;
+        dot = fmaf(gv, d, dot);
+        sq = fmaf(d, d, sq);
+    }
+    part[(size_t)blockIdx.y * B + b] = dot;
+    part[((size_t)chunks + blockIdx.y) * B + b] = sq;
+}
+
+// sufficient-decrease test per searching restart; partial sums in a fixed
+// order (FP64); on failure eta halves; after the last trial the point is
+// taken anyway.  pending counts the restarts still searching.
+__global__ void k_fista_accept(int B, int chunks, const float *__restrict__ part, const float *__restrict__ Fy,
+                               const float *__restrict__ Fz, float *eta, int32_t *searching, float *Fout, int last,
+                               int32_t *pending)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B || !searching[b]) return;
+    double dot = 0.0, sq = 0.0;
+    for (int c = 0; c < chunks; ++c) {
+        dot += (double)part[(size_t)c * B + b];
+        sq += (double)part[((size_t)chunks + c) * B + b];
+    }
+    const float e = eta[b];
+    const double bound = (double)Fy[b] + dot + sq / (2.0 * (double)e);
+    const bool ok = (double)Fz[b] <= bound;
+    if (!ok) eta[b] = 0.5f * e;
+    if (ok || last) {
+        searching[b] = 0;
+        if (Fout) Fout[b] = Fz[b];
+    } else {
+        atomicAdd(pending, 1);
+    }
+}
+
+__global__ void k_fista_coef(int B, const int32_t *__restrict__ active, float *t, float *coef)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    if (!active[b]) {
+        coef[b] = 0.f;
+        return;
+    }
+    const float tk = t[b];
+    const float tn = 0.5f * (1.f + sqrtf(1.f + 4.f * tk * tk));
+    coef[b] = (tk - 1.f) / tn;
+    t[b] = tn;
+}
+
+__global__ void k_fista_momentum(int64_t total, int B, const int32_t *__restrict__ active,
+                                 const float *__restrict__ coef, const float *__restrict__ z, float *x, float *y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int b = (int)(i % B);
+    if (!active[b]) return;
+    const float zv = z[i], xv = x[i];
+    y[i] = fmaf(coef[b], zv - xv, zv);
+    x[i] = zv;
+}
+
+int fista_rows(int n, int B)
+{
+    // enough (chunk, restart-tile) blocks to cover the chip, at least 8 variables per chunk
+    const int tiles = (B + 255) / 256;
+    int rows = (int)std::max<int64_t>(8, ((int64_t)n * tiles + 2047) / 2048);
+    return std::min(rows, std::max(n, 1));
+}
+
+hipError_t launch_fista_begin(int B, const float *eta, int32_t *active, int32_t *searching, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fista_begin, dim3((B + 255) / 256), dim3(256), 0, s, B, eta, active, searching);
+    return hipGetLastError();
+}
+
+hipError_t launch_fista_trial(int n, int B, const float *y, const float *g, const float *eta, const int32_t *searching,
+                              float *z, float *part, hipStream_t s)
+{
+    const int rows = fista_rows(n, B);
+    const int chunks = (n + rows - 1) / rows;
+    hipLaunchKernelGGL(k_fista_trial, dim3((B + 255) / 256, chunks), dim3(256), 0, s, n, B, rows, chunks, y, g, eta,
+                       searching, z, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_fista_accept(int n, int B, const float *part, const float *Fy, const float *Fz, float *eta,
+                               int32_t *searching, float *Fout, int last, int32_t *pending, hipStream_t s)
+{
+    const int rows = fista_rows(n, B);
+    const int chunks = (n + rows - 1) / rows;
+    hipLaunchKernelGGL(k_fista_accept, dim3((B + 255) / 256), dim3(256), 0, s, B, chunks, part, Fy, Fz, eta, searching,
+                       Fout, last, pending);
+    return hipGetLastError();
+}
+
+hipError_t launch_fista_finish(int n, int B, const int32_t *active, float *t, float *coef, const float *z, float *x,
+                               float *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fista_coef, dim3((B + 255) / 256), dim3(256), 0, s, B, active, t, coef);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t total = (int64_t)n * B;
+    hipLaunchKernelGGL(k_fista_momentum, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total, B, active, coef,
+                       z, x, y);
+    return hipGetLastError();
+}
+
+}  // namespace ffsat

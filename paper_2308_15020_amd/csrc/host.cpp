@@ -1009,6 +1009,14 @@ extern "C" ffsat_status ffsat_plan_destroy(ffsat_plan *pl)
     (void)hipFree(pl->d_cpart);
     (void)hipFree(pl->d_ctmp);
     (void)hipFree(pl->d_scratch_x);
+    (void)hipFree(pl->d_fz);
+    (void)hipFree(pl->d_fg);
+    (void)hipFree(pl->d_fFy);
+    (void)hipFree(pl->d_fFz);
+    (void)hipFree(pl->d_fpartial);
+    (void)hipFree(pl->d_fcoef);
+    (void)hipFree(pl->d_fflags);
+    (void)hipFree(pl->d_fpending);
     if (pl->cap) (void)hipStreamDestroy(pl->cap);
     for (int q = 0; q < ffsat_plan::N_SIDE; ++q) {
         if (pl->side[q]) (void)hipStreamDestroy(pl->side[q]);
@@ -1255,6 +1263,61 @@ extern "C" ffsat_status ffsat_erwa_update(ffsat_plan *pl, const int32_t *U, floa
     if (!pl || !U) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
     if (!(alpha >= 0.f && alpha <= 1.f)) return fail(FFSAT_E_INVALID_ARG, "alpha must be in [0, 1]");
     HIPCHK(launch_erwa(pl->p->m, U, pl->p->d_w, alpha, pl->d_umax, (hipStream_t)stream));
+    return FFSAT_OK;
+}
+
+// FISTA workspace of a plan (first use)
+static ffsat_status ensure_fista(ffsat_plan *pl)
+{
+    if (pl->d_fz) return FFSAT_OK;
+    const size_t nb = (size_t)pl->p->n * (size_t)pl->B, B = (size_t)pl->B;
+    const int rows = fista_rows(pl->p->n, pl->B);
+    const size_t chunks = (size_t)((pl->p->n + rows - 1) / rows);
+    HIPCHK(hipMalloc(&pl->d_fz, nb * sizeof(float)));
+    HIPCHK(hipMalloc(&pl->d_fg, nb * sizeof(float)));
+    HIPCHK(hipMalloc(&pl->d_fFy, B * sizeof(float)));
+    HIPCHK(hipMalloc(&pl->d_fFz, B * sizeof(float)));
+    HIPCHK(hipMalloc(&pl->d_fpartial, 2 * chunks * B * sizeof(float)));
+    HIPCHK(hipMalloc(&pl->d_fcoef, B * sizeof(float)));
+    HIPCHK(hipMalloc(&pl->d_fflags, 2 * B * sizeof(int32_t)));
+    HIPCHK(hipMalloc(&pl->d_fpending, sizeof(int32_t)));
+    pl->device_bytes += (int64_t)((2 * nb + 2 * chunks * B + 3 * B) * sizeof(float) + 2 * B * sizeof(int32_t) + 4);
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_fista(ffsat_plan *pl, float *x, float *y, float *eta, float *t, int32_t T,
+                                    int32_t max_ls, float *F, void *stream)
+{
+    if (!pl || !x || !y || !eta || !t) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    if (T < 0) return fail(FFSAT_E_INVALID_ARG, "T must be >= 0 (got %d)", T);
+    if (max_ls < 1 || max_ls > 64) return fail(FFSAT_E_INVALID_ARG, "max_ls must be in [1, 64] (got %d)", max_ls);
+    hipStream_t s = (hipStream_t)stream;
+    ffsat_status st = ensure_workspace(pl, IO_F32);
+    if (st != FFSAT_OK) return st;
+    if ((st = ensure_fista(pl)) != FFSAT_OK) return st;
+    const int n = pl->p->n, B = pl->B;
+    int32_t *active = pl->d_fflags, *searching = pl->d_fflags + B;
+    for (int it = 0; it < T; ++it) {
+        HIPCHK(launch_fista_begin(B, eta, active, searching, s));
+        if ((st = run_eval<float>(pl, y, pl->d_fFy, pl->d_fg, nullptr, nullptr, nullptr, nullptr, true, nullptr, 0.f,
+                                  s)) != FFSAT_OK)
+            return st;
+        for (int q = 0; q < max_ls; ++q) {
+            HIPCHK(launch_fista_trial(n, B, y, pl->d_fg, eta, searching, pl->d_fz, pl->d_fpartial, s));
+            if ((st = run_eval<float>(pl, pl->d_fz, pl->d_fFz, nullptr, nullptr, nullptr, nullptr, nullptr, true,
+                                      nullptr, 0.f, s)) != FFSAT_OK)
+                return st;
+            HIPCHK(launch_fill_i32(pl->d_fpending, 1, 0, s));
+            HIPCHK(launch_fista_accept(n, B, pl->d_fpartial, pl->d_fFy, pl->d_fFz, eta, searching, F,
+                                       q == max_ls - 1 ? 1 : 0, pl->d_fpending, s));
+            if (q == max_ls - 1) break;
+            int32_t pending = 0;
+            HIPCHK(hipMemcpyAsync(&pending, pl->d_fpending, sizeof pending, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (pending == 0) break;
+        }
+        HIPCHK(launch_fista_finish(n, B, active, t, pl->d_fcoef, pl->d_fz, x, y, s));
+    }
     return FFSAT_OK;
 }
 

@@ -165,6 +165,11 @@ struct ffsat_plan {
     int32_t *d_flag = nullptr;       // debug non-finite flag
     int32_t *d_umax = nullptr;       // [1024] partial maxima of the weight update
     float *d_scratch_x = nullptr;    // autotuner input
+    // FISTA workspace (allocated on first use): trial point, gradient at y,
+    // objective at y and at the trial, partial sums, flags, momentum, counter
+    float *d_fz = nullptr, *d_fg = nullptr, *d_fFy = nullptr, *d_fFz = nullptr, *d_fpartial = nullptr;
+    float *d_fcoef = nullptr;
+    int32_t *d_fflags = nullptr, *d_fpending = nullptr;
     hipStream_t cap = nullptr;       // capture stream for graphs
     // three side streams: with the caller's stream, one per hardware queue
     // of HIP's default of four per process
@@ -228,6 +233,14 @@ hipError_t launch_nonfinite_f32(int64_t total, const float *x, int32_t *flag, hi
 hipError_t launch_nonfinite_f64(int64_t total, const double *x, int32_t *flag, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_scratch_points(float *x, int64_t total, uint32_t seed, hipStream_t s);
+int fista_rows(int n, int B);
+hipError_t launch_fista_begin(int B, const float *eta, int32_t *active, int32_t *searching, hipStream_t s);
+hipError_t launch_fista_trial(int n, int B, const float *y, const float *g, const float *eta, const int32_t *searching,
+                              float *z, float *part, hipStream_t s);
+hipError_t launch_fista_accept(int n, int B, const float *part, const float *Fy, const float *Fz, float *eta,
+                               int32_t *searching, float *Fout, int last, int32_t *pending, hipStream_t s);
+hipError_t launch_fista_finish(int n, int B, const int32_t *active, float *t, float *coef, const float *z, float *x,
+                               float *y, hipStream_t s);
 
 // number of F-partial rows of a bin list
 int fpart_rows_of(const std::vector<Bin> &bins);

@@ -40,7 +40,8 @@ def _assignment(x: torch.Tensor, b: int) -> np.ndarray:
 def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: float = 0.05,
           alpha: float = 0.4, weighting: bool = True, policy: str = "ROF",
           x0: Optional[torch.Tensor] = None, seed: int = 0, time_limit: Optional[float] = None,
-          plan: Optional[Plan] = None, log: bool = False) -> SolveResult:
+          plan: Optional[Plan] = None, log: bool = False, optimizer: str = "pgd",
+          max_ls: int = 15) -> SolveResult:
     """Alg. 1: returns at the first round in which some restart's rounded point
     satisfies every constraint (decided by the exact checker).
 
@@ -49,7 +50,12 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
     'R' = plain random restarts).  weighting=False keeps w fixed.
     x0: initial points [n][B] (device, float32); default U[-1, 1] drawn by the
     library's random phase.
+    optimizer: 'pgd' (T projected steps of size eta, captured as one graph) or
+    'fista' (T accelerated iterations with backtracking from step eta, Alg. 5's
+    line search; the state restarts after every rephasing).
     """
+    if optimizer not in ("pgd", "fista"):
+        raise ValueError("optimizer must be 'pgd' or 'fista'")
     t_start = time.perf_counter()
     dev = problem.device
     plan = plan or Plan(problem, B)
@@ -63,8 +69,12 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
     history = []
     best = -1
     steps = 0
+    state = plan.fista_state(x, eta) if optimizer == "fista" else None
     for r in range(rounds):
-        plan.run_steps(x, T, eta)
+        if state is None:
+            plan.run_steps(x, T, eta)
+        else:
+            plan.fista(x, state, T, max_ls=max_ls)
         steps += T
         chk = plan.round_check(x, want=("n_sat", "U"))
         n_sat = chk["n_sat"]
@@ -82,4 +92,6 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
             plan.erwa_update(chk["U"], alpha)
         phase = policy[r % len(policy)]
         plan.rephase(x, PHASE_MODE[phase], seed=seed * 1000003 + r + 1)
+        if state is not None:
+            state = plan.fista_state(x, eta)
     return SolveResult(False, -1, None, len(history), steps, time.perf_counter() - t_start, best, history)

@@ -124,3 +124,13 @@ def test_solver_planted(ffs, policy, weighting):
     if res.solved:
         x = np.where(res.assignment, -1.0, 1.0)[:, None]
         assert int(oracle.check(inst, x)["n_sat"][0]) == inst.m
+
+
+def test_time_to_solve_harness_runs(ffs):
+    """The learned-vs-uniform harness end to end on a tiny planted budget."""
+    from paper_2308_15020_amd import tts
+    s = tts.main(["--train", "2", "--test", "2", "--B", "64", "--rounds", "4", "--T", "20", "--epochs", "3",
+                  "--planted"])
+    assert s["instances"] == 2
+    assert 0.0 <= s["solve_rate"]["uniform"] <= 1.0 and 0.0 <= s["solve_rate"]["learned"] <= 1.0
+    assert np.isfinite(s["train_loss"]).all()
