@@ -102,7 +102,12 @@ typedef struct {
     int32_t use_graphs;      /* 1: ffsat_run_steps replays a captured hipGraph */
     const char *tune_cache;  /* JSON file for tuned shapes (NULL = in memory only) */
     int32_t reserved[8];     /* reserved[0] = 1: launch all bins on the caller's stream
-                                (no internal side streams); others must be 0 */
+                                (no internal side streams); reserved[1]: launch
+                                structure of the FP32 evaluation, 0 automatic (the
+                                autotuner times the others and keeps the fastest),
+                                1 one launch per bin, 2 one grouped launch for all
+                                bins, 3 a grouped launch for the root-of-unity bins
+                                with the others beside it; others must be 0 */
 } ffsat_plan_opts;
 
 /* ---- errors ------------------------------------------------------------- */
@@ -241,6 +246,17 @@ ffsat_status ffsat_weight_grad(ffsat_plan *plan, const float *con_val, const flo
  * Device buffers; gx may alias grad. */
 ffsat_status ffsat_vjp(ffsat_plan *plan, const float *grad, const float *con_val, const float *gF,
                        float *gx, float *gw, void *stream);
+
+/* T fused iterations on device data (Alg. 1's inner loop with the paper's
+ * certificate check every step): each evaluates F, checks the rounded point
+ * exactly and takes the projected step of x_t (as ffsat_eval_step), then,
+ * when alpha > 0, updates the weights from that iteration's violation counts
+ * (as ffsat_erwa_update).  F [B], n_sat [B], U [m] receive the last
+ * iteration's values (each optional; U required when alpha > 0).  With
+ * graphs enabled the sequence is captured once per argument set and
+ * replayed.  Errors as ffsat_eval_step. */
+ffsat_status ffsat_run_iters(ffsat_plan *plan, float *x, int32_t T, float eta, float alpha, float *F,
+                             int32_t *n_sat, int32_t *U, void *stream);
 
 /* ---- accelerated projected gradient (Alg. 5 and the line search it names) */
 

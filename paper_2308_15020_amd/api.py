@@ -102,7 +102,7 @@ class Plan:
     """A batch size B bound to a problem, with its device workspace."""
 
     def __init__(self, problem: Problem, B: int, autotune: bool = False, use_graphs: bool = True,
-                 tune_cache: Optional[str] = None, side_streams: bool = True):
+                 tune_cache: Optional[str] = None, side_streams: bool = True, mode: str = "auto"):
         self.problem = problem
         self.B = int(B)
         self.device = problem.device
@@ -111,6 +111,10 @@ class Plan:
         o.use_graphs = 1 if use_graphs else 0
         o.tune_cache = tune_cache.encode() if tune_cache else None
         o.reserved[0] = 0 if side_streams else 1
+        modes = {"auto": 0, "per_bin": 1, "group_all": 2, "group_dft": 3}
+        if mode not in modes:
+            raise ValueError(f"mode must be one of {sorted(modes)}")
+        o.reserved[1] = modes[mode]
         h = C.c_void_p()
         check(lib().ffsat_plan_create(problem.handle, self.B, C.byref(o), C.byref(h)))
         self._h = h
@@ -243,6 +247,19 @@ class Plan:
             _need(mask, (self.B,), torch.int32, self.device, "mask")
         check(lib().ffsat_rephase(self.handle, _ptr(x), int(mode), int(seed) & ((1 << 64) - 1), _ptr(mask),
                                   _stream(self.device)))
+
+    def run_iters(self, x: torch.Tensor, T: int, eta: float, alpha: float = 0.0, out: Optional[dict] = None) -> dict:
+        """T fused iterations (objective, exact check, projected step, then the
+        adaptive weights when alpha > 0), replayed from a captured graph."""
+        self._x(x)
+        dev = self.device
+        out = dict(out or {})
+        out.setdefault("F", torch.empty(self.B, dtype=torch.float32, device=dev))
+        out.setdefault("n_sat", torch.empty(self.B, dtype=torch.int32, device=dev))
+        out.setdefault("U", torch.empty(self.m, dtype=torch.int32, device=dev))
+        check(lib().ffsat_run_iters(self.handle, _ptr(x), int(T), float(eta), float(alpha), _ptr(out["F"]),
+                                    _ptr(out["n_sat"]), _ptr(out["U"]), _stream(dev)))
+        return out
 
     def fista_state(self, x: torch.Tensor, eta0: float) -> dict:
         """Fresh FISTA state for the points x: y = x, eta = eta0, t = 1."""

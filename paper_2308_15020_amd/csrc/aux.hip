@@ -213,10 +213,10 @@ hipError_t launch_assign_bits_f64(int n, int B, const double *x, uint32_t *bits,
 // ---------------------------------------------------------------- adaptive weights
 
 // ERWA (Prop. 3): w_c <- (1 - alpha) w_c + alpha U_c / max_c' U_c'.
-// Up to ERWA_ONE_BLOCK constraints one 1024-thread block does the maximum
-// (eight loads in flight per thread, wave reductions) and the update;
-// beyond that, per-block partial maxima first, then every block of the
-// update reduces the (at most 1024) partials itself.
+// Up to ERWA_ONE_BLOCK constraints one launch: every 1024-thread block
+// computes the maximum (eight loads in flight per thread, wave reductions)
+// and updates its slice; beyond that, per-block partial maxima first, then
+// every block of the update reduces the (at most 1024) partials itself.
 constexpr int ERWA_ONE_BLOCK = 1 << 16;
 
 __device__ __forceinline__ int32_t block_max_1024(int32_t v, int32_t *red)
@@ -226,9 +226,10 @@ __device__ __forceinline__ int32_t block_max_1024(int32_t v, int32_t *red)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) red[wave] = v;
     __syncthreads();
+    // every lane of every wave ends with the block maximum (counts are >= 0)
     v = lane < (int)(blockDim.x >> 6) ? red[lane] : 0;
 #pragma unroll
-    for (int d = 8; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
     return v;
 }
 
@@ -247,12 +248,15 @@ __device__ __forceinline__ int32_t strided_max(int m, const int32_t *__restrict_
     return mx;
 }
 
+// every block finds the maximum itself (1024 threads, eight loads in
+// flight each), then updates its own 1024 weights
 __global__ __launch_bounds__(1024) void k_erwa_one(int m, const int32_t *__restrict__ U, float *w, float alpha)
 {
     __shared__ int32_t red[16];
     const int32_t umax = block_max_1024(strided_max(m, U, threadIdx.x, 1024), red);
     const float inv = umax > 0 ? 1.0f / (float)umax : 0.0f;
-    for (int c = threadIdx.x; c < m; c += 1024) {
+    const int c = blockIdx.x * 1024 + threadIdx.x;
+    if (c < m) {
         const float r = umax > 0 ? (float)U[c] * inv : 0.0f;
         w[c] = (1.0f - alpha) * w[c] + alpha * r;
     }
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(1024) void k_erwa_apply(int m, int nparts, const in
 hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, int32_t *part, hipStream_t s)
 {
     if (m <= ERWA_ONE_BLOCK) {
-        hipLaunchKernelGGL(k_erwa_one, dim3(1), dim3(1024), 0, s, m, U, w, alpha);
+        hipLaunchKernelGGL(k_erwa_one, dim3((m + 1023) / 1024), dim3(1024), 0, s, m, U, w, alpha);
         return hipGetLastError();
     }
     const int nparts = std::min(1024, (m + 8191) / 8192);

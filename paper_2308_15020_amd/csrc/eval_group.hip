@@ -1,0 +1,74 @@
+// Grouped evaluation launch: every FP32-arithmetic bin of the FP32
+// evaluation in one grid.  A host-built block table gives each 4-wave block
+// its bin (entry) and first unit; the host orders the blocks longest-first
+// with the memory-bound real-chain blocks spread among them.  One launch
+// keeps all CUs busy across bins of very different cost, with no
+// cross-stream synchronisation.
+#include "eval_kernel.h"
+
+namespace ffsat {
+
+// Kernel variants of a grouped launch (FP32 arithmetic, the shapes of the
+// FP32 shape rule): (SEG, L) for L = 1 with SEG in {4, 8, 16, 24, 32}, and
+// for L in {2, 4, 8, 16} with SEG in {24, 32}; real chains first, then
+// root-of-unity products.
+#define FFSAT_GROUP_SHAPES(X, CPLX, BASE)                                                             \
+    X(BASE + 0, 4, 1, CPLX) X(BASE + 1, 8, 1, CPLX) X(BASE + 2, 16, 1, CPLX) X(BASE + 3, 24, 1, CPLX) \
+    X(BASE + 4, 32, 1, CPLX) X(BASE + 5, 24, 2, CPLX) X(BASE + 6, 32, 2, CPLX)                        \
+    X(BASE + 7, 24, 4, CPLX) X(BASE + 8, 32, 4, CPLX) X(BASE + 9, 24, 8, CPLX)                        \
+    X(BASE + 10, 32, 8, CPLX) X(BASE + 11, 24, 16, CPLX) X(BASE + 12, 32, 16, CPLX)
+constexpr int GROUP_SHAPES = 13;
+
+int group_variant(int ct, int cls, int seg, int L)
+{
+    if (ct != CT_F32) return -1;
+    const int base = cls == CLASS_DFT ? GROUP_SHAPES : 0;
+#define X(ID, S, LL, C) \
+    if (seg == S && L == LL) return ID + base;
+    FFSAT_GROUP_SHAPES(X, false, 0)
+#undef X
+    return -1;
+}
+
+// Each 256-thread block: entry blk.x; fg == 1: units blk.y .. blk.y + 3,
+// one per wave; fg == 4: unit blk.y, its frequencies over the 4 waves.
+__global__ __launch_bounds__(256) void k_eval_group(EvalArgs<float> a, const float *__restrict__ xin,
+                                                    const ConDesc *__restrict__ con,
+                                                    const int32_t *__restrict__ lits,
+                                                    const float *__restrict__ wts,
+                                                    const TypeT<float> *__restrict__ types,
+                                                    const FreqT<float> *__restrict__ freqs,
+                                                    const GroupEntry *__restrict__ ent,
+                                                    const int2 *__restrict__ blk)
+{
+    extern __shared__ __align__(16) char group_lds[];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int2 bw = blk[blockIdx.x];
+    const GroupEntry e = ent[__builtin_amdgcn_readfirstlane(bw.x)];
+    const Span sp{e.first, e.count, e.cpw, e.n_rb, e.fpart_row0};
+    const int fg = e.fg;
+    const int unit = fg > 1 ? bw.y : bw.y + wave;
+    const int wg = fg > 1 ? wave : 0;
+    switch (e.variant) {
+#define X(ID, S, LL, C)                                                                                    \
+    case ID:                                                                                               \
+        eval_unit<float, float, S, LL, C>(a, sp, unit, xin, con, lits, wts, types, freqs, fg, wg, group_lds); \
+        break;
+        FFSAT_GROUP_SHAPES(X, false, 0)
+        FFSAT_GROUP_SHAPES(X, true, GROUP_SHAPES)
+#undef X
+    default: break;
+    }
+}
+
+hipError_t launch_eval_group_f32(const EvalArgs<float> &a, const GroupEntry *ent, const int2 *blk, int nblk,
+                                 size_t lds, hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eval_group, dim3((unsigned)nblk), dim3(256), lds, s, a, a.x, a.con, a.lit, a.w,
+                       reinterpret_cast<const TypeT<float> *>(a.types),
+                       reinterpret_cast<const FreqT<float> *>(a.freqs), ent, blk);
+    return hipGetLastError();
+}
+
+}  // namespace ffsat

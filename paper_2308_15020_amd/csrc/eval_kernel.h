@@ -220,16 +220,23 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
 
 // The work of one wave: unit = (chunk of sp.cpw constraints of the range
 // sp.first .. sp.first + sp.count, restart block rb).  `unit` must be
-// wave-uniform.  Read-only inputs are separate __restrict__ arguments: the
-// compiler may then read uniform descriptors and coefficients through the
-// scalar cache.
+// wave-uniform.  Root-of-unity kernels may split a unit's frequencies over
+// fg <= 4 waves of one workgroup (wave wg takes a contiguous share, the
+// last one also the real chain); waves 1.. pass their partial gradients and
+// values through LDS (`lds`: (fg - 1) * (SEG + 1) * 64 values) and wave 0
+// adds them in wave order and writes the results.  Read-only inputs are
+// separate __restrict__ arguments: the compiler may then read uniform
+// descriptors and coefficients through the scalar cache.
 template <typename IO, typename CT, int SEG, int L, bool CPLX>
 __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, const int unit,
                                           const IO *__restrict__ xin, const ConDesc *__restrict__ con,
                                           const int32_t *__restrict__ lits, const float *__restrict__ wts,
                                           const TypeT<CT> *__restrict__ types,
-                                          const FreqT<CT> *__restrict__ freqs)
+                                          const FreqT<CT> *__restrict__ freqs, const int fg_in, const int wg_in,
+                                          void *lds)
 {
+    const int fg = CPLX ? fg_in : 1;
+    const int wg = CPLX ? wg_in : 0;
     constexpr int RPW = 64 / L;
     const int lane = threadIdx.x & 63;
     const int n_chunks = (sp.count + sp.cpw - 1) / sp.cpw;
@@ -259,10 +266,17 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
         // Branch-free: all literal loads (indices clamped into the
         // constraint), then all point loads, so that a lane waits for two
         // memory round trips per constraint rather than two per position.
-        int nv = min(max(k - i0, 0), SEG);   // positions of this lane inside the constraint
+        // kernels with long constraints: per-constraint copies the compiler cannot
+        // hoist; otherwise it keeps i0 + t and the bit constants 1 << t in
+        // SEG registers each across the whole kernel (real-chain kernels run
+        // many constraints per wave and profit from the hoisting)
+        int i0c = i0;
+        uint32_t one = 1u;
+        if constexpr (CPLX || L > 1) asm volatile("" : "+v"(i0c), "+v"(one));
+        int nv = min(max(k - i0c, 0), SEG);   // positions of this lane inside the constraint
         int lt[SEG];
 #pragma unroll
-        for (int t = 0; t < SEG; ++t) lt[t] = lits[d.off + min(i0 + t, k - 1)];
+        for (int t = 0; t < SEG; ++t) lt[t] = lits[d.off + min(i0c + t, k - 1)];
         IO xr[SEG];
 #pragma unroll
         for (int t = 0; t < SEG; ++t) xr[t] = xin[(size_t)(lt[t] & 0x7fffffff) * a.B + bb];
@@ -275,13 +289,13 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
             const CT xv = (CT)xr[t];
             lv[t] = in ? (neg ? -xv : xv) : ty.pad;
             const bool vt = xr[t] < IO(0);
-            negm |= ((in && neg) ? 1u : 0u) << t;
-            tmask |= ((in && (neg != vt)) ? 1u : 0u) << t;
+            negm |= ((in && neg) ? one : 0u) << t;
+            tmask |= ((in && (neg != vt)) ? one : 0u) << t;
         }
         // opaque: otherwise the stores re-derive the sign bits from the
         // loaded literals, which then stay live across the frequency loop
         asm volatile("" : "+v"(negm));
-        if (a.want_check) {
+        if (a.want_check && wg == 0) {
             const int cnt = group_sum_int<L>(__popc(tmask));
             const bool sat = d.chk >= 0 ? (cnt >= d.chk) : ((cnt & 1) == (d.chk == -2 ? 1 : 0));
             const bool uns = !sat && bok && j == 0;
@@ -306,21 +320,22 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
         CT we = 0;
         if constexpr (CPLX) {
             const int n1 = ty.n1, nf = ty.n1 + ty.n2;
-            FreqT<CT> fr = freqs[ty.tab];
+            const int f0 = (nf * wg) / fg, f1 = (nf * (wg + 1)) / fg;   // this wave's frequencies
+            FreqT<CT> fr = freqs[ty.tab + f0];
 #pragma unroll 1
-            for (int f = 0; f < n1; ++f) {
+            for (int f = f0; f < min(f1, n1); ++f) {
                 const FreqT<CT> nxt = freqs[ty.tab + f + 1];   // table has one entry of padding
                 freq_pass<CT, SEG, L, 1>(j, lv, gr, fr, we);
                 fr = nxt;
             }
 #pragma unroll 1
-            for (int f = n1; f < nf; ++f) {
+            for (int f = max(f0, n1); f < f1; ++f) {
                 const FreqT<CT> nxt = freqs[ty.tab + f + 1];
                 freq_pass<CT, SEG, L, 2>(j, lv, gr, fr, we);
                 fr = nxt;
             }
         }
-        if (ty.has_real) {
+        if (ty.has_real && wg == fg - 1) {
             // real chain: prod (alpha + beta l); padding factors are exactly 1
             CT q[SEG];
             CT P = 1;
@@ -337,6 +352,37 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
             for (int t = SEG - 1; t >= 0; --t) {
                 gr[t] = fmaT(q[t], S, gr[t]);
                 if (t > 0) S = S * fmaT(ty.beta, lv[t], ty.alpha);
+            }
+        }
+        if constexpr (CPLX) {
+            if (fg > 1) {
+                // partial sums of the fg waves, added in wave order by wave 0
+                // one base address per wave, positions at constant offsets
+                CT *red = reinterpret_cast<CT *>(lds) + lane;
+                if (wg > 0) {
+                    CT *dst = red + (wg - 1) * (SEG + 1) * 64;
+                    // opaque base: positions become immediate offsets of one
+                    // address instead of SEG hoisted address registers
+                    asm volatile("" : "+v"(dst));
+#pragma unroll
+                    for (int t = 0; t < SEG; ++t) dst[t * 64] = gr[t];
+                    dst[SEG * 64] = we;
+                }
+                __syncthreads();
+                if (wg == 0) {
+#pragma unroll
+                    for (int q = 1; q < 4; ++q) {
+                        if (q < fg) {
+                            const CT *src = red + (q - 1) * (SEG + 1) * 64;
+                            asm volatile("" : "+v"(src));
+#pragma unroll
+                            for (int t = 0; t < SEG; ++t) gr[t] += src[t * 64];
+                            we += src[SEG * 64];
+                        }
+                    }
+                }
+                __syncthreads();   // the next constraint reuses the buffer
+                if (wg > 0) continue;
             }
         }
         we += ty.cst;
@@ -357,7 +403,7 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
             }
         }
     }
-    if (j == 0 && bok) {
+    if (j == 0 && bok && wg == 0) {
         const size_t row = (size_t)(sp.fpart_row0 + chunk) * a.B + b;
         if (a.do_value) a.fpart[row] = (IO)facc;
         if (a.want_check) a.cpart[row] = nunsat;
@@ -373,12 +419,15 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs<IO> a, const IO *__restri
                                               const TypeT<CT> *__restrict__ types,
                                               const FreqT<CT> *__restrict__ freqs)
 {
+    extern __shared__ __align__(16) char eval_lds[];
     // the wave index is uniform: say so, so that everything derived from it
     // (constraint descriptors, coefficient tables, loop bounds) stays scalar
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int unit = blockIdx.x * (blockDim.x >> 6) + wave;
+    const bool split = CPLX && a.fg > 1;   // one unit per block, its frequencies over the waves
+    const int unit = split ? (int)blockIdx.x : (int)blockIdx.x * (int)(blockDim.x >> 6) + wave;
     const Span sp{a.first, a.count, a.cpw, a.n_rb, a.fpart_row0};
-    eval_unit<IO, CT, SEG, L, CPLX>(a, sp, unit, xin, con, lits, wts, types, freqs);
+    eval_unit<IO, CT, SEG, L, CPLX>(a, sp, unit, xin, con, lits, wts, types, freqs, split ? a.fg : 1,
+                                    split ? wave : 0, eval_lds);
 }
 
 template <typename IO>
@@ -445,16 +494,18 @@ static hipError_t launch_fn(EvalFn<IO> fn, const Bin &bin, const EvalArgs<IO> &a
     const int n_chunks = (a.count + a.cpw - 1) / a.cpw;
     const int64_t units = (int64_t)n_chunks * a.n_rb;
     if (units <= 0) return hipSuccess;
-    const int wpb = bin.wpb;
-    const int64_t blocks = (units + wpb - 1) / wpb;
+    const bool split = bin.cls == CLASS_DFT && a.fg > 1;
+    const int wpb = split ? a.fg : bin.wpb;
+    const int64_t blocks = split ? units : (units + wpb - 1) / wpb;
+    const size_t lds = split ? (size_t)(a.fg - 1) * (bin.seg + 1) * 64 * (fn.ct == CT_F32 ? 4 : 8) : 0;
     if (fn.ct == CT_F32) {
         auto k = reinterpret_cast<typename EvalFnT<IO>::template type<float>>(const_cast<void *>(fn.fn));
-        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, a, a.x, a.con, a.lit, a.w,
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, s, a, a.x, a.con, a.lit, a.w,
                            reinterpret_cast<const TypeT<float> *>(a.types),
                            reinterpret_cast<const FreqT<float> *>(a.freqs));
     } else {
         auto k = reinterpret_cast<typename EvalFnT<IO>::template type<double>>(const_cast<void *>(fn.fn));
-        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), 0, s, a, a.x, a.con, a.lit, a.w,
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * wpb), lds, s, a, a.x, a.con, a.lit, a.w,
                            reinterpret_cast<const TypeT<double> *>(a.types),
                            reinterpret_cast<const FreqT<double> *>(a.freqs));
     }

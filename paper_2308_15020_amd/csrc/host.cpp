@@ -618,15 +618,19 @@ static std::string bin_key(const ffsat_plan *pl, const Bin &b, int io)
     return buf;
 }
 
-static std::map<std::string, std::pair<int, int>> read_cache(const std::string &path)
+struct Shape {
+    int cpw, wpb, fg;
+};
+
+static std::map<std::string, Shape> read_cache(const std::string &path)
 {
-    std::map<std::string, std::pair<int, int>> out;
+    std::map<std::string, Shape> out;
     std::ifstream f(path);
     if (!f) return out;
     std::stringstream ss;
     ss << f.rdbuf();
     const std::string s = ss.str();
-    // entries: "key": [cpw, wpb]
+    // entries: "key": [cpw, wpb, fg] (fg optional, default 1)
     size_t i = 0;
     while ((i = s.find('"', i)) != std::string::npos) {
         const size_t j = s.find('"', i + 1);
@@ -634,21 +638,23 @@ static std::map<std::string, std::pair<int, int>> read_cache(const std::string &
         const std::string key = s.substr(i + 1, j - i - 1);
         const size_t lb = s.find('[', j), rb = s.find(']', j);
         if (lb == std::string::npos || rb == std::string::npos) break;
-        int cpw = 0, wpb = 0;
-        if (sscanf(s.c_str() + lb + 1, "%d , %d", &cpw, &wpb) == 2 && cpw > 0 && wpb > 0) out[key] = {cpw, wpb};
+        int cpw = 0, wpb = 0, fg = 1;
+        const int got = sscanf(s.c_str() + lb + 1, "%d , %d , %d", &cpw, &wpb, &fg);
+        if (got >= 2 && cpw > 0 && wpb > 0 && (got == 2 || (fg == 1 || fg == 2 || fg == 4)))
+            out[key] = {cpw, wpb, got == 3 ? fg : 1};
         i = rb + 1;
     }
     return out;
 }
 
-static void write_cache(const std::string &path, const std::map<std::string, std::pair<int, int>> &m)
+static void write_cache(const std::string &path, const std::map<std::string, Shape> &m)
 {
     std::ofstream f(path);
     if (!f) return;
     f << "{\n";
     size_t q = 0;
     for (const auto &kv : m) {
-        f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
+        f << "  \"" << kv.first << "\": [" << kv.second.cpw << ", " << kv.second.wpb << ", " << kv.second.fg << "]"
           << (++q < m.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -673,6 +679,7 @@ static EvalArgs<IO> base_args(ffsat_plan *pl, int io, const IO *x, IO *con_val, 
     a.want_grad = want_grad ? 1 : 0;
     a.do_value = 1;
     a.want_check = 0;
+    a.fg = 1;
     return a;
 }
 
@@ -712,6 +719,76 @@ static void prof_end(ffsat_plan *pl, hipStream_t s, ProfRec &r)
     pl->prof_pending.push_back(r);
 }
 
+// Block table of the grouped FP32 evaluation (MODE_GROUP_ALL: every bin with
+// a grouped variant; MODE_GROUP_DFT: the root-of-unity bins, the others run
+// on a side stream beside it).  Units of a bin are (chunk,
+// restart block); a block runs 4 units (fg = 1) or one unit with its
+// frequencies over 4 waves (fg = 4).  Blocks are ordered longest first
+// (estimated VALU work), with the real-chain blocks spread evenly among the
+// root-of-unity ones so that every CU mixes memory- and ALU-bound waves.
+static ffsat_status build_groups(ffsat_plan *pl)
+{
+    (void)hipFree(pl->d_gent);
+    (void)hipFree(pl->d_gblk);
+    pl->d_gent = nullptr;
+    pl->d_gblk = nullptr;
+    pl->gblocks = 0;
+    pl->glds = 0;
+    pl->gsolo.clear();
+    if (!pl->grouped) return FFSAT_OK;
+    const std::vector<Bin> &bins = pl->bins[IO_F32];
+    std::vector<GroupEntry> ent;
+    struct Blk {
+        int2 b;
+        double cost;
+    };
+    std::vector<Blk> dft, real;
+    int row0 = 0;
+    for (int i = 0; i < (int)bins.size(); ++i) {
+        const Bin &b = bins[i];
+        const int v = group_variant(b.ct, b.cls, b.seg, b.L);
+        const int fg = b.cls == CLASS_DFT ? b.fg : 1;
+        const int rows = (b.count + b.cpw - 1) / b.cpw;
+        if (v < 0 || (fg != 1 && fg != 4) || (pl->mode == MODE_GROUP_DFT && b.cls != CLASS_DFT)) {
+            pl->gsolo.push_back(i);
+            row0 += rows;
+            continue;
+        }
+        const int rpw = 64 / b.L;
+        const int n_rb = (pl->B + rpw - 1) / rpw;
+        GroupEntry e{v, b.first, b.count, b.cpw, n_rb, row0, fg, 0};
+        const int ei = (int)ent.size();
+        ent.push_back(e);
+        const int64_t units = (int64_t)rows * n_rb;
+        const double unit_cost = b.cost / std::max(1, b.count) * b.cpw * rpw;
+        if (fg == 4) {
+            for (int64_t u = 0; u < units; ++u) dft.push_back({make_int2(ei, (int)u), unit_cost});
+            pl->glds = std::max(pl->glds, (size_t)3 * (b.seg + 1) * 64 * sizeof(float));
+        } else {
+            for (int64_t u = 0; u < units; u += 4)
+                (b.cls == CLASS_DFT ? dft : real).push_back({make_int2(ei, (int)u), 4 * unit_cost});
+        }
+        row0 += rows;
+    }
+    if (ent.empty()) return FFSAT_OK;
+    std::stable_sort(dft.begin(), dft.end(), [](const Blk &x, const Blk &y) { return x.cost > y.cost; });
+    std::vector<int2> order;
+    order.reserve(dft.size() + real.size());
+    size_t di = 0, ri = 0;
+    const double nd = (double)dft.size(), nr = (double)real.size();
+    while (di < dft.size() || ri < real.size()) {
+        // keep the fraction of real blocks emitted equal to that of root-of-unity ones
+        const bool take_real = ri < real.size() && (di >= dft.size() || (ri + 0.5) / nr <= (di + 0.5) / nd);
+        order.push_back(take_real ? real[ri++].b : dft[di++].b);
+    }
+    HIPCHK(hipMalloc(&pl->d_gent, ent.size() * sizeof(GroupEntry)));
+    HIPCHK(hipMemcpy(pl->d_gent, ent.data(), ent.size() * sizeof(GroupEntry), hipMemcpyHostToDevice));
+    HIPCHK(hipMalloc(&pl->d_gblk, order.size() * sizeof(int2)));
+    HIPCHK(hipMemcpy(pl->d_gblk, order.data(), order.size() * sizeof(int2), hipMemcpyHostToDevice));
+    pl->gblocks = (int)order.size();
+    return FFSAT_OK;
+}
+
 // Launches every bin of the evaluation.  With side streams, the bins are
 // spread over them (heaviest first, each to the least loaded stream) after a
 // fork event on s, and s waits for all of them: independent bins overlap,
@@ -721,6 +798,50 @@ static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream
 {
     const Layout &Ly = pl->p->lay[io];
     const std::vector<Bin> &bins = pl->bins[io];
+    if constexpr (sizeof(IO) == 4) {
+        if (pl->grouped && pl->gblocks > 0) {
+            // bins without a grouped variant: on a side stream beside the
+            // grouped launch when there is one, else before it
+            hipError_t e;
+            hipStream_t ss = s;
+            const bool fork = pl->side[0] != nullptr && !pl->gsolo.empty();
+            if (fork) {
+                if ((e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return e;
+                if ((e = hipStreamWaitEvent(pl->side[0], pl->ev_fork, 0)) != hipSuccess) return e;
+                ss = pl->side[0];
+            }
+            for (int bi : pl->gsolo) {
+                const Bin &b = bins[bi];
+                int row0 = 0;
+                for (int q = 0; q < bi; ++q) row0 += (bins[q].count + bins[q].cpw - 1) / bins[q].cpw;
+                a.first = b.first;
+                a.count = b.count;
+                a.cpw = b.cpw;
+                a.fg = b.fg;
+                a.n_rb = (pl->B + (64 / b.L) - 1) / (64 / b.L);
+                a.fpart_row0 = row0;
+                a.types = b.ct == CT_F32 ? (const void *)Ly.d_t32 : (const void *)Ly.d_t64;
+                a.freqs = b.ct == CT_F32 ? (const void *)Ly.d_f32 : (const void *)Ly.d_f64;
+                ProfRec rec;
+                prof_begin(pl, ss, prof_active(pl, s), rec, io, bi);
+                e = launch_eval_bin_f32(b, a, ss);
+                prof_end(pl, ss, rec);
+                if (e != hipSuccess) return e;
+            }
+            a.types = (const void *)Ly.d_t32;
+            a.freqs = (const void *)Ly.d_f32;
+            ProfRec rec;
+            prof_begin(pl, s, prof_active(pl, s), rec, io, -2);
+            e = launch_eval_group_f32(a, pl->d_gent, pl->d_gblk, pl->gblocks, pl->glds, s);
+            prof_end(pl, s, rec);
+            if (e != hipSuccess) return e;
+            if (fork) {
+                if ((e = hipEventRecord(pl->ev_join[0], pl->side[0])) != hipSuccess) return e;
+                if ((e = hipStreamWaitEvent(s, pl->ev_join[0], 0)) != hipSuccess) return e;
+            }
+            return hipSuccess;
+        }
+    }
     const bool fork = pl->side[0] != nullptr && bins.size() > 1;
     hipError_t e;
     constexpr int NS = ffsat_plan::N_SIDE + 1;   // slot 0 is the caller's stream
@@ -735,6 +856,7 @@ static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream
         a.first = b.first;
         a.count = b.count;
         a.cpw = b.cpw;
+        a.fg = b.fg;
         a.n_rb = (pl->B + (64 / b.L) - 1) / (64 / b.L);
         a.fpart_row0 = row0;
         a.types = b.ct == CT_F32 ? (const void *)Ly.d_t32 : (const void *)Ly.d_t64;
@@ -820,8 +942,19 @@ static void default_shapes(ffsat_plan *pl)
     for (int io = 0; io < 2; ++io) {
         for (Bin &b : pl->bins[io]) {
             b.wpb = 4;
+            b.fg = 1;
             if (b.cls == CLASS_DFT) {
+                // one constraint per unit; split the frequencies over up to 4
+                // waves until the bin alone has about 3 waves per SIMD
                 b.cpw = 1;
+                if (pl->grouped) {
+                    // the grouped launch fills the chip anyway: split the
+                    // frequencies of long constraints only (fg 1 or 4)
+                    b.fg = b.maxk >= 32 ? 4 : 1;
+                } else {
+                    const int64_t units = (int64_t)b.count * ((pl->B + (64 / b.L) - 1) / (64 / b.L));
+                    while (b.fg < 4 && units * b.fg < 3072) b.fg *= 2;
+                }
                 continue;
             }
             const int cap = b.maxk <= 8 ? 16 : (b.maxk <= 32 ? 8 : 2);
@@ -832,6 +965,62 @@ static void default_shapes(ffsat_plan *pl)
         }
         pl->fpart_rows[io] = fpart_rows_of(pl->bins[io]);
     }
+}
+
+template <typename IO>
+static ffsat_status run_eval(ffsat_plan *pl, const IO *x, IO *F, IO *grad, IO *con_val, int32_t *n_sat,
+                             uint32_t *unsat_bits, int32_t *U, bool do_value, float *x_step, float eta,
+                             hipStream_t s);
+
+// With MODE_AUTO, times one full FP32 evaluation with the fused step (on the
+// tuner's scratch points, step size 0) under each launch structure and keeps
+// the fastest; the choice is cached with the shapes.
+static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cache, hipStream_t s)
+{
+    if (!pl->mode_auto) return FFSAT_OK;
+    char kb[160];
+    snprintf(kb, sizeof kb, "gfx950|mode|B%d|n%d|m%d|nnz%lld|bins%zu", pl->B, pl->p->n, pl->p->m,
+             (long long)pl->p->nnz, pl->bins[IO_F32].size());
+    const std::string key = kb;
+    auto hit = cache.find(key);
+    int best_mode = MODE_GROUP_DFT;
+    if (hit != cache.end() && hit->second.cpw >= MODE_PER_BIN && hit->second.cpw <= MODE_GROUP_DFT) {
+        best_mode = hit->second.cpw;
+    } else {
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        float best = 1e30f;
+        for (int m : {MODE_GROUP_DFT, MODE_GROUP_ALL, MODE_PER_BIN}) {
+            pl->mode = m;
+            pl->grouped = m != MODE_PER_BIN;
+            ffsat_status st = build_groups(pl);
+            if (st != FFSAT_OK) return st;
+            if ((st = run_eval<float>(pl, pl->d_scratch_x, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true,
+                                      pl->d_scratch_x, 0.f, s)) != FFSAT_OK)
+                return st;
+            HIPCHK(hipEventRecord(e0, s));
+            const int reps = 5;
+            for (int r = 0; r < reps; ++r)
+                if ((st = run_eval<float>(pl, pl->d_scratch_x, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                          true, pl->d_scratch_x, 0.f, s)) != FFSAT_OK)
+                    return st;
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best * 0.97f) {
+                best = ms;
+                best_mode = m;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        cache[key] = Shape{best_mode, 1, 1};   // stored in the cpw field
+    }
+    pl->mode = best_mode;
+    pl->grouped = best_mode != MODE_PER_BIN;
+    return FFSAT_OK;
 }
 
 extern "C" ffsat_status ffsat_plan_tune(ffsat_plan *pl, void *stream)
@@ -846,7 +1035,7 @@ extern "C" ffsat_status ffsat_plan_tune(ffsat_plan *pl, void *stream)
         pl->device_bytes += (int64_t)(sizeof(float) * (size_t)p->n * (size_t)pl->B);
         HIPCHK(launch_scratch_points(pl->d_scratch_x, (int64_t)p->n * pl->B, 12345u, s));
     }
-    std::map<std::string, std::pair<int, int>> cache;
+    std::map<std::string, Shape> cache;
     if (!pl->tune_cache.empty()) cache = read_cache(pl->tune_cache);
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -859,8 +1048,9 @@ extern "C" ffsat_status ffsat_plan_tune(ffsat_plan *pl, void *stream)
         const std::string key = bin_key(pl, b, IO_F32);
         auto hit = cache.find(key);
         if (hit != cache.end()) {
-            b.cpw = hit->second.first;
-            b.wpb = hit->second.second;
+            b.cpw = hit->second.cpw;
+            b.wpb = hit->second.wpb;
+            b.fg = b.cls == CLASS_DFT ? hit->second.fg : 1;
             continue;
         }
         a.first = b.first;
@@ -870,41 +1060,60 @@ extern "C" ffsat_status ffsat_plan_tune(ffsat_plan *pl, void *stream)
         a.types = b.ct == CT_F32 ? (const void *)Ly.d_t32 : (const void *)Ly.d_t64;
         a.freqs = b.ct == CT_F32 ? (const void *)Ly.d_f32 : (const void *)Ly.d_f64;
         float best = 1e30f;
-        int bc = b.cpw, bw = b.wpb;
-        const int cpws[] = {1, 2, 4, 8, 16, 32, 64};
-        const int wpbs[] = {1, 2, 4};
-        for (int cpw : cpws) {
-            if (cpw > 1 && cpw > b.count) break;
-            for (int wpb : wpbs) {
-                Bin t = b;
-                t.cpw = cpw;
-                t.wpb = wpb;
-                a.cpw = cpw;
-                HIPCHK(launch_eval_bin_f32(t, a, s));
-                HIPCHK(hipEventRecord(e0, s));
-                const int reps = 3;
-                for (int r = 0; r < reps; ++r) HIPCHK(launch_eval_bin_f32(t, a, s));
-                HIPCHK(hipEventRecord(e1, s));
-                HIPCHK(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                ms /= reps;
-                if (ms < best * 0.97f) { best = ms; bc = cpw; bw = wpb; }
+        Shape bs{b.cpw, b.wpb, b.fg};
+        std::vector<Shape> cands;
+        if (b.cls == CLASS_DFT) {
+            for (int fg : {1, 2, 4})
+                for (int cpw : {1, 2, 4}) {
+                    if (pl->grouped && fg == 2) break;   // grouped blocks take fg 1 or 4
+                    if (cpw > 1 && cpw > b.count) break;
+                    if (fg == 1) {
+                        for (int wpb : {1, 2, 4}) cands.push_back({cpw, wpb, 1});
+                    } else {
+                        cands.push_back({cpw, fg, fg});
+                    }
+                }
+        } else {
+            for (int cpw : {1, 2, 4, 8, 16, 32, 64}) {
+                if (cpw > 1 && cpw > b.count) break;
+                for (int wpb : {1, 2, 4}) cands.push_back({cpw, wpb, 1});
             }
         }
-        b.cpw = bc;
-        b.wpb = bw;
-        cache[key] = {bc, bw};
+        for (const Shape &c : cands) {
+            Bin t = b;
+            t.cpw = c.cpw;
+            t.wpb = c.wpb;
+            t.fg = c.fg;
+            a.cpw = c.cpw;
+            a.fg = c.fg;
+            HIPCHK(launch_eval_bin_f32(t, a, s));
+            HIPCHK(hipEventRecord(e0, s));
+            const int reps = 3;
+            for (int r = 0; r < reps; ++r) HIPCHK(launch_eval_bin_f32(t, a, s));
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            ms /= reps;
+            if (ms < best * 0.97f) { best = ms; bs = c; }
+        }
+        b.cpw = bs.cpw;
+        b.wpb = bs.wpb;
+        b.fg = bs.fg;
+        cache[key] = bs;
         dirty = true;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (dirty && !pl->tune_cache.empty()) write_cache(pl->tune_cache, cache);
     pl->fpart_rows[IO_F32] = fpart_rows_of(pl->bins[IO_F32]);
     // cached graphs baked the old shapes
     for (auto &kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
     pl->graphs.clear();
     pl->tuned = true;
+    const size_t n_cached = cache.size();
+    if ((st = tune_mode(pl, cache, s)) != FFSAT_OK) return st;
+    if ((st = build_groups(pl)) != FFSAT_OK) return st;
+    if ((dirty || cache.size() != n_cached) && !pl->tune_cache.empty()) write_cache(pl->tune_cache, cache);
     return FFSAT_OK;
 }
 
@@ -919,6 +1128,14 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
     pl->B = B;
     pl->bins[0] = split_bins(p->lay[0].bins, p->lay[0].cost_prefix);
     pl->bins[1] = split_bins(p->lay[1].bins, p->lay[1].cost_prefix);
+    const int req = opts ? opts->reserved[1] : MODE_AUTO;
+    if (req < MODE_AUTO || req > MODE_GROUP_DFT) {
+        delete pl;
+        return fail(FFSAT_E_INVALID_ARG, "reserved[1] (evaluation mode) must be in 0..3");
+    }
+    pl->mode_auto = req == MODE_AUTO;
+    pl->mode = pl->mode_auto ? MODE_GROUP_DFT : req;   // the tuner may change an automatic choice
+    pl->grouped = pl->mode != MODE_PER_BIN;
     default_shapes(pl);
     pl->use_graphs = opts ? opts->use_graphs != 0 : true;
     if (opts && opts->tune_cache) pl->tune_cache = opts->tune_cache;
@@ -937,6 +1154,7 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
         }
         if (e != hipSuccess) st = fail(FFSAT_E_HIP, "side streams: %s", hipGetErrorString(e));
     }
+    if (st == FFSAT_OK) st = build_groups(pl);
     if (st == FFSAT_OK && opts && opts->autotune) {
         st = ffsat_plan_tune(pl, nullptr);
         if (st == FFSAT_OK) {
@@ -999,6 +1217,8 @@ extern "C" ffsat_status ffsat_plan_destroy(ffsat_plan *pl)
     }
     for (hipEvent_t e : pl->prof_pool) (void)hipEventDestroy(e);
     for (auto &kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+    (void)hipFree(pl->d_gent);
+    (void)hipFree(pl->d_gblk);
     for (int io = 0; io < 2; ++io) {
         (void)hipFree(pl->d_slot[io]);
         (void)hipFree(pl->d_fpart[io]);
@@ -1031,7 +1251,11 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
 {
     if (!pl || !buf || len == 0) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
     std::ostringstream o;
-    o << "{\"B\": " << pl->B << ", \"tuned\": " << (pl->tuned ? "true" : "false") << ", \"bins\": {";
+    static const char *mode_names[] = {"auto", "per_bin", "group_all", "group_dft"};
+    o << "{\"B\": " << pl->B << ", \"tuned\": " << (pl->tuned ? "true" : "false") << ", \"mode\": \""
+      << mode_names[pl->mode] << "\"" << ", \"mode_auto\": " << (pl->mode_auto ? "true" : "false")
+      << ", \"grouped\": " << (pl->grouped && pl->gblocks > 0 ? "true" : "false") << ", \"group_blocks\": " << pl->gblocks
+      << ", \"solo_bins\": " << pl->gsolo.size() << ", \"bins\": {";
     for (int io = 0; io < 2; ++io) {
         o << (io ? ", " : "") << "\"" << (io ? "f64" : "f32") << "\": [";
         for (size_t i = 0; i < pl->bins[io].size(); ++i) {
@@ -1042,7 +1266,12 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
               << ", \"lits\": " << b.lits << ", \"cost\": " << b.cost << ", \"flops_per_restart\": " << b.flops
               << ", \"bytes_per_restart\": " << b.bytes << ", \"positions_per_restart\": " << b.exec_pos
               << ", \"cpw\": " << b.cpw
-              << ", \"wpb\": " << b.wpb << "}";
+              << ", \"wpb\": " << b.wpb << ", \"fg\": " << b.fg << ", \"in_group\": "
+              << ((io == IO_F32 && pl->grouped && pl->gblocks > 0 &&
+                   std::find(pl->gsolo.begin(), pl->gsolo.end(), (int)i) == pl->gsolo.end())
+                      ? "true"
+                      : "false")
+              << "}";
         }
         o << "]";
     }
@@ -1181,6 +1410,37 @@ extern "C" ffsat_status ffsat_step_f64(ffsat_plan *pl, double *x, const double *
     return FFSAT_OK;
 }
 
+// The executable graph of a launch sequence, captured once per key on the
+// plan's capture stream (side-stream bins become parallel branches) and kept
+// (at most 16 per plan).
+template <typename Body>
+static ffsat_status cached_graph(ffsat_plan *pl, const GraphKey &key, Body body, hipGraphExec_t *out)
+{
+    auto it = pl->graphs.find(key);
+    if (it == pl->graphs.end()) {
+        if (!pl->cap) HIPCHK(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+        const hipError_t e = body(pl->cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(pl->cap, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(FFSAT_E_HIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) return fail(FFSAT_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e3));
+        if (pl->graphs.size() >= 16) {
+            for (auto &kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+            pl->graphs.clear();
+        }
+        it = pl->graphs.emplace(key, ex).first;
+    }
+    *out = it->second;
+    return FFSAT_OK;
+}
+
 static hipError_t enqueue_step_iter(ffsat_plan *pl, float *x, float eta, float *F, hipStream_t s)
 {
     const ffsat_status st = run_eval<float>(pl, x, F, nullptr, nullptr, nullptr, nullptr, nullptr, true, x, eta, s);
@@ -1200,31 +1460,55 @@ extern "C" ffsat_status ffsat_run_steps(ffsat_plan *pl, float *x, int32_t T, flo
         for (int t = 0; t < T; ++t) HIPCHK(enqueue_step_iter(pl, x, eta, t == T - 1 ? F_last : nullptr, s));
         return FFSAT_OK;
     }
-    const GraphKey key{x, T, eta, F_last};
-    auto it = pl->graphs.find(key);
-    if (it == pl->graphs.end()) {
-        if (!pl->cap) HIPCHK(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
-        HIPCHK(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+    const GraphKey key{0, x, T, eta, 0.f, F_last, nullptr, nullptr};
+    hipGraphExec_t ex = nullptr;
+    if ((st = cached_graph(pl, key, [&](hipStream_t cs) {
+             hipError_t e = hipSuccess;
+             for (int t = 0; t < T && e == hipSuccess; ++t)
+                 e = enqueue_step_iter(pl, x, eta, t == T - 1 ? F_last : nullptr, cs);
+             return e;
+         }, &ex)) != FFSAT_OK)
+        return st;
+    HIPCHK(hipGraphLaunch(ex, s));
+    return FFSAT_OK;
+}
+
+// T fused iterations: objective, exact check and projected step of x_t, then
+// the adaptive weights from that iteration's violation counts (alpha > 0)
+static hipError_t enqueue_iter(ffsat_plan *pl, float *x, float eta, float alpha, float *F, int32_t *n_sat, int32_t *U,
+                               hipStream_t s)
+{
+    if (run_eval<float>(pl, x, F, nullptr, nullptr, n_sat, nullptr, U, true, x, eta, s) != FFSAT_OK)
+        return hipErrorUnknown;
+    if (alpha > 0.f) return launch_erwa(pl->p->m, U, pl->p->d_w, alpha, pl->d_umax, s);
+    return hipSuccess;
+}
+
+extern "C" ffsat_status ffsat_run_iters(ffsat_plan *pl, float *x, int32_t T, float eta, float alpha, float *F,
+                                        int32_t *n_sat, int32_t *U, void *stream)
+{
+    if (!pl || !x) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    if (T < 0) return fail(FFSAT_E_INVALID_ARG, "T must be >= 0");
+    if (!(alpha >= 0.f && alpha <= 1.f)) return fail(FFSAT_E_INVALID_ARG, "alpha must be in [0, 1]");
+    if (alpha > 0.f && !U) return fail(FFSAT_E_INVALID_ARG, "U is required when alpha > 0");
+    if (T == 0) return FFSAT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    ffsat_status st = ensure_workspace(pl, IO_F32);
+    if (st != FFSAT_OK) return st;
+    if ((st = check_finite<float>(pl, x, s)) != FFSAT_OK) return st;
+    auto body = [&](hipStream_t cs) {
         hipError_t e = hipSuccess;
-        for (int t = 0; t < T && e == hipSuccess; ++t)
-            e = enqueue_step_iter(pl, x, eta, t == T - 1 ? F_last : nullptr, pl->cap);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(pl->cap, &g);
-        if (e != hipSuccess || e2 != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return fail(FFSAT_E_HIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
-        }
-        hipGraphExec_t ex = nullptr;
-        hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e3 != hipSuccess) return fail(FFSAT_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e3));
-        if (pl->graphs.size() >= 16) {
-            for (auto &kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
-            pl->graphs.clear();
-        }
-        it = pl->graphs.emplace(key, ex).first;
+        for (int t = 0; t < T && e == hipSuccess; ++t) e = enqueue_iter(pl, x, eta, alpha, F, n_sat, U, cs);
+        return e;
+    };
+    if (!pl->use_graphs) {
+        HIPCHK(body(s));
+        return FFSAT_OK;
     }
-    HIPCHK(hipGraphLaunch(it->second, s));
+    const GraphKey key{1, x, T, eta, alpha, F, n_sat, U};
+    hipGraphExec_t ex = nullptr;
+    if ((st = cached_graph(pl, key, body, &ex)) != FFSAT_OK) return st;
+    HIPCHK(hipGraphLaunch(ex, s));
     return FFSAT_OK;
 }
 

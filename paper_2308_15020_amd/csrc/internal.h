@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ffsat.h"
@@ -62,6 +63,7 @@ struct Bin {
     double bytes = 0;           // algorithmic HBM bytes per restart (gathers + slot writes)
     double exec_pos = 0;        // literal positions executed per restart (with padding)
     int cpw = 1, wpb = 4;       // tile shape: constraints per wave, waves per block
+    int fg = 1;                 // root-of-unity bins: waves splitting one unit's frequencies
 };
 
 struct ProfRec {
@@ -124,6 +126,7 @@ struct EvalArgs {
     const void *freqs;
     int B, first, count, cpw, n_rb, fpart_row0;
     int want_grad, do_value, want_check, wm;
+    int fg;                // root-of-unity bins: waves sharing one unit's frequencies (1, 2 or 4)
 };
 
 // A wave's constraint range and tiling (one bin, or one entry of a grouped launch).
@@ -131,16 +134,23 @@ struct Span {
     int first, count, cpw, n_rb, fpart_row0;
 };
 
+// One bin of a grouped evaluation launch: its kernel variant and tiling.
+struct GroupEntry {
+    int32_t variant, first, count, cpw, n_rb, fpart_row0, fg, pad;
+};
+
+// Launch structure of the FP32 evaluation.
+enum { MODE_AUTO = 0, MODE_PER_BIN = 1, MODE_GROUP_ALL = 2, MODE_GROUP_DFT = 3 };
+
 struct GraphKey {
+    int32_t kind;          // 0: ffsat_run_steps, 1: ffsat_run_iters
     const void *x;
     int32_t T;
-    float eta;
-    const void *F;
+    float eta, alpha;
+    const void *F, *n_sat, *U;
     bool operator<(const GraphKey &o) const {
-        if (x != o.x) return x < o.x;
-        if (T != o.T) return T < o.T;
-        if (eta != o.eta) return eta < o.eta;
-        return F < o.F;
+        return std::tie(kind, x, T, eta, alpha, F, n_sat, U) <
+               std::tie(o.kind, o.x, o.T, o.eta, o.alpha, o.F, o.n_sat, o.U);
     }
 };
 
@@ -171,6 +181,16 @@ struct ffsat_plan {
     float *d_fcoef = nullptr;
     int32_t *d_fflags = nullptr, *d_fpending = nullptr;
     hipStream_t cap = nullptr;       // capture stream for graphs
+    // grouped FP32 evaluation: one launch over a block table (entries =
+    // bins); bins without a grouped variant are launched one by one
+    bool grouped = true;             // mode GROUP_ALL or GROUP_DFT
+    int mode = 0;                    // MODE_* (evaluation launch structure)
+    bool mode_auto = false;          // chosen by the tuner
+    ffsat::GroupEntry *d_gent = nullptr;
+    int2 *d_gblk = nullptr;
+    int gblocks = 0;
+    size_t glds = 0;
+    std::vector<int> gsolo;          // bin indices launched on their own
     // three side streams: with the caller's stream, one per hardware queue
     // of HIP's default of four per process
     static constexpr int N_SIDE = 3;
@@ -193,6 +213,9 @@ namespace ffsat {
 // kernels (eval.hip / aux.hip)
 hipError_t launch_eval_bin_f32(const Bin &bin, const EvalArgs<float> &a, hipStream_t s);
 hipError_t launch_eval_bin_f64(const Bin &bin, const EvalArgs<double> &a, hipStream_t s);
+int group_variant(int ct, int cls, int seg, int L);
+hipError_t launch_eval_group_f32(const EvalArgs<float> &a, const GroupEntry *ent, const int2 *blk, int nblk,
+                                 size_t lds, hipStream_t s);
 bool eval_variant_exists(int io, int ct, int cls, int seg, int L);
 
 // Reduction after the evaluation kernels: gradient (or fused projected step
