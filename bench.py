@@ -59,6 +59,27 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(roof):
+    """HBM bytes per launch of the grouped evaluation kernel from the committed
+    rocprofv3 counter summary, if the kernel sources are unchanged since the
+    counters were taken (else None)."""
+    if not roof.get("kernel", "").startswith("grouped evaluation launch"):
+        return None
+    from paper_2308_15020_amd.profsum import kernel_source_hash
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "eval_group_mixed2000_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_hash() or "traffic_bytes_per_launch" not in kv:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(inst, x_np, budget_s=12.0):
     """FP64 oracle on the host: the same instance and points (all restarts
     when one pass takes under a third of the budget, else a leading subset),
@@ -227,6 +248,7 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "gradient reduction + step",
                 "avg_launch_ms": dom["avg_ms"], "bytes_per_launch": nbytes}
+    roof["traffic"] = measured_traffic(roof)
     kernels = []
     for k in sorted(kern, key=lambda k: -k["total_ms"]):
         name = "reduce" if k["bin"] == -1 else "grouped eval" if k["bin"] == -2 else (

@@ -2,6 +2,9 @@
 
   python -m paper_2308_15020_amd.profsum trace <..._kernel_trace.csv>
       per (kernel, grid) dispatch count, average / total duration, share
+  python -m paper_2308_15020_amd.profsum traffic <FETCH csv> <WRITE csv> --copy-mib M [--kernel k_eval_group]
+      HBM bytes per dispatch of one kernel from the two counter passes,
+      scaled by the plain elementwise kernel; with the kernel sources' hash
   python -m paper_2308_15020_amd.profsum pmc <..._counter_collection.csv> [--copy-mib M]
       per (kernel, grid) average of each counter per dispatch; with
       --copy-mib, the same counters for the largest plain copy dispatch and
@@ -66,14 +69,74 @@ def pmc(path: str, copy_mib: float = 0.0, top: int = 25) -> str:
     return "\n".join(lines)
 
 
+def kernel_source_hash() -> str:
+    """SHA-256 over the sources that make up the evaluation kernels."""
+    import hashlib
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for f in ("eval_kernel.h", "eval_group.hip", "eval_f32.hip", "internal.h"):
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _per_dispatch(path, counter, match):
+    tot, calls = 0.0, set()
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter and match in r["Kernel_Name"]:
+            tot += float(r["Counter_Value"])
+            calls.add(r["Dispatch_Id"])
+    return tot / max(1, len(calls)), len(calls)
+
+
+def _calib(path, counter, copy_mib):
+    best = 0.0
+    acc = defaultdict(float)
+    calls = defaultdict(set)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter and "elementwise" in r["Kernel_Name"].lower():
+            acc[r["Kernel_Name"]] += float(r["Counter_Value"])
+            calls[r["Kernel_Name"]].add(r["Dispatch_Id"])
+    for k in acc:
+        best = max(best, acc[k] / len(calls[k]))
+    return copy_mib * 1024 / best if best > 0 else None
+
+
+def traffic(fetch_csv, write_csv, kernel, copy_mib):
+    """HBM bytes per dispatch of `kernel`: FETCH_SIZE and WRITE_SIZE (KiB)
+    scaled by what they read for a plain elementwise kernel of copy_mib MiB."""
+    f, nf = _per_dispatch(fetch_csv, "FETCH_SIZE", kernel)
+    w, nw = _per_dispatch(write_csv, "WRITE_SIZE", kernel)
+    sf, sw = _calib(fetch_csv, "FETCH_SIZE", copy_mib), _calib(write_csv, "WRITE_SIZE", copy_mib)
+    rb = f * 1024 * sf
+    wb = w * 1024 * sw
+    return "\n".join([
+        f"traffic_kernel: {kernel}",
+        f"source_sha256: {kernel_source_hash()}",
+        f"fetch_kib_per_dispatch: {f:.1f} ({nf} dispatches), scale {sf:.4f}",
+        f"write_kib_per_dispatch: {w:.1f} ({nw} dispatches), scale {sw:.4f}",
+        f"read_bytes_per_launch: {rb:.0f}",
+        f"write_bytes_per_launch: {wb:.0f}",
+        f"traffic_bytes_per_launch: {rb + wb:.0f}",
+    ])
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("kind", choices=["trace", "pmc"])
+    ap.add_argument("kind", choices=["trace", "pmc", "traffic"])
     ap.add_argument("csv")
+    ap.add_argument("csv2", nargs="?", default=None, help="traffic: the WRITE_SIZE csv")
     ap.add_argument("--copy-mib", type=float, default=0.0)
+    ap.add_argument("--kernel", default="k_eval_group")
     ap.add_argument("--top", type=int, default=25)
     a = ap.parse_args()
-    print(trace(a.csv, a.top) if a.kind == "trace" else pmc(a.csv, a.copy_mib, a.top))
+    if a.kind == "trace":
+        print(trace(a.csv, a.top))
+    elif a.kind == "pmc":
+        print(pmc(a.csv, a.copy_mib, a.top))
+    else:
+        print(traffic(a.csv, a.csv2, a.kernel, a.copy_mib))
 
 
 if __name__ == "__main__":
