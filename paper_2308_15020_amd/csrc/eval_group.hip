@@ -9,15 +9,15 @@
 namespace ffsat {
 
 // Kernel variants of a grouped launch (FP32 arithmetic, the shapes of the
-// FP32 shape rule): (SEG, L) for L = 1 with SEG in {4, 8, 16, 24, 32}, and
-// for L in {2, 4, 8, 16} with SEG in {24, 32}; real chains first, then
+// FP32 shape rule): (SEG, L) for L = 1 with SEG in {4, 8, 16, 24}, and for
+// L in {2, 4, 8, 16} with SEG in {16, 24}; real chains first, then
 // root-of-unity products.
 #define FFSAT_GROUP_SHAPES(X, CPLX, BASE)                                                             \
     X(BASE + 0, 4, 1, CPLX) X(BASE + 1, 8, 1, CPLX) X(BASE + 2, 16, 1, CPLX) X(BASE + 3, 24, 1, CPLX) \
-    X(BASE + 4, 32, 1, CPLX) X(BASE + 5, 24, 2, CPLX) X(BASE + 6, 32, 2, CPLX)                        \
-    X(BASE + 7, 24, 4, CPLX) X(BASE + 8, 32, 4, CPLX) X(BASE + 9, 24, 8, CPLX)                        \
-    X(BASE + 10, 32, 8, CPLX) X(BASE + 11, 24, 16, CPLX) X(BASE + 12, 32, 16, CPLX)
-constexpr int GROUP_SHAPES = 13;
+    X(BASE + 4, 16, 2, CPLX) X(BASE + 5, 24, 2, CPLX) X(BASE + 6, 16, 4, CPLX)                        \
+    X(BASE + 7, 24, 4, CPLX) X(BASE + 8, 16, 8, CPLX) X(BASE + 9, 24, 8, CPLX)                        \
+    X(BASE + 10, 16, 16, CPLX) X(BASE + 11, 24, 16, CPLX)
+constexpr int GROUP_SHAPES = 12;
 
 int group_variant(int ct, int cls, int seg, int L)
 {
@@ -32,7 +32,10 @@ int group_variant(int ct, int cls, int seg, int L)
 
 // Each 256-thread block: entry blk.x; fg == 1: units blk.y .. blk.y + 3,
 // one per wave; fg == 4: unit blk.y, its frequencies over the 4 waves.
-__global__ __launch_bounds__(256) void k_eval_group(EvalArgs<float> a, const float *__restrict__ xin,
+// Register budget of 4 waves per SIMD (128 VGPRs; the longest variants spill
+// a few values outside their inner loops): measured faster than 3 waves
+// without spills.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_eval_group(EvalArgs<float> a, const float *__restrict__ xin,
                                                     const ConDesc *__restrict__ con,
                                                     const int32_t *__restrict__ lits,
                                                     const float *__restrict__ wts,

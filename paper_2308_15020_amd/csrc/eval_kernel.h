@@ -445,7 +445,8 @@ struct EvalFn {
 };
 
 // Segment shapes: L = 1 with SEG in {4, 8, ..., SMAX}; L >= 2 with SEG in
-// (SMAX/2, SMAX], multiples of 4 (SMAX = 32 for FP32 arithmetic, 16 for FP64).
+// (SMAX/2, SMAX], multiples of 4 (SMAX = 32 for FP32 arithmetic, 16 for FP64),
+// and SEG = 16 at every L.
 template <typename IO, typename CT, int SEG, int L, bool CPLX>
 static EvalFn<IO> handle()
 {
@@ -462,7 +463,7 @@ static EvalFn<IO> pick_L(int seg)
     case 4: if constexpr (L == 1) return handle<IO, CT, 4, L, CPLX>(); break;
     case 8: if constexpr (L == 1) return handle<IO, CT, 8, L, CPLX>(); break;
     case 12: if constexpr (L == 1 || sizeof(CT) == 8) return handle<IO, CT, 12, L, CPLX>(); break;
-    case 16: if constexpr (L == 1 || sizeof(CT) == 8) return handle<IO, CT, 16, L, CPLX>(); break;
+    case 16: return handle<IO, CT, 16, L, CPLX>();
     case 20: if constexpr (sizeof(CT) == 4) return handle<IO, CT, 20, L, CPLX>(); break;
     case 24: if constexpr (sizeof(CT) == 4) return handle<IO, CT, 24, L, CPLX>(); break;
     case 28: if constexpr (sizeof(CT) == 4) return handle<IO, CT, 28, L, CPLX>(); break;

@@ -190,18 +190,26 @@ TypeD dft_type(const std::vector<cld> &hv, int k, int L, int s)
 }
 
 // Segment shape of a constraint of length k: L lanes (a power of two) of SEG
-// positions each (4, 8, or a multiple of 8 up to 32 for FP32 arithmetic;
+// positions each (4, 8, 16 or 24 for FP32 arithmetic, 32 past k = 384;
 // 4, 8, 12 or 16 for FP64), L * SEG >= k, the smallest such L and then the
 // smallest SEG.  Fewer distinct shapes mean fewer, larger kernel launches.
 void shape_for(int ct, int k, int &seg, int &L)
 {
-    const int smax = ct == CT_F32 ? 32 : 16;
+    // FP32: segments of at most 24 literals (the register budget of 3+ waves
+    // per SIMD), 32 only where 16 lanes of 24 do not reach (k > 384)
+    int smax = ct == CT_F32 ? 24 : 16;
     L = 1;
-    while ((k + L - 1) / L > smax) L <<= 1;
+    while ((k + L - 1) / L > smax) {
+        if (ct == CT_F32 && L == 16) {
+            smax = 32;
+            break;
+        }
+        L <<= 1;
+    }
     const int s = (k + L - 1) / L;
     if (s <= 4) seg = 4;
     else if (s <= 8) seg = 8;
-    else if (ct == CT_F32) seg = ((s + 7) / 8) * 8;
+    else if (ct == CT_F32) seg = ((s + 7) / 8) * 8;   // 16, 24 (32 only past k = 384)
     else seg = ((s + 3) / 4) * 4;
 }
 
