@@ -357,27 +357,27 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
         if constexpr (CPLX) {
             if (fg > 1) {
                 // partial sums of the fg waves, added in wave order by wave 0
-                // one base address per wave, positions at constant offsets
-                CT *red = reinterpret_cast<CT *>(lds) + lane;
+                // one base index per wave, positions at constant offsets; the
+                // index (not the pointer, which must stay an LDS pointer) is
+                // opaque so that the compiler does not hoist SEG addresses
+                CT *red = reinterpret_cast<CT *>(lds);
                 if (wg > 0) {
-                    CT *dst = red + (wg - 1) * (SEG + 1) * 64;
-                    // opaque base: positions become immediate offsets of one
-                    // address instead of SEG hoisted address registers
-                    asm volatile("" : "+v"(dst));
+                    int base = (wg - 1) * (SEG + 1) * 64 + lane;
+                    asm volatile("" : "+v"(base));
 #pragma unroll
-                    for (int t = 0; t < SEG; ++t) dst[t * 64] = gr[t];
-                    dst[SEG * 64] = we;
+                    for (int t = 0; t < SEG; ++t) red[base + t * 64] = gr[t];
+                    red[base + SEG * 64] = we;
                 }
                 __syncthreads();
                 if (wg == 0) {
 #pragma unroll
                     for (int q = 1; q < 4; ++q) {
                         if (q < fg) {
-                            const CT *src = red + (q - 1) * (SEG + 1) * 64;
-                            asm volatile("" : "+v"(src));
+                            int base = (q - 1) * (SEG + 1) * 64 + lane;
+                            asm volatile("" : "+v"(base));
 #pragma unroll
-                            for (int t = 0; t < SEG; ++t) gr[t] += src[t * 64];
-                            we += src[SEG * 64];
+                            for (int t = 0; t < SEG; ++t) gr[t] += red[base + t * 64];
+                            we += red[base + SEG * 64];
                         }
                     }
                 }
