@@ -36,16 +36,31 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 VALU_PEAK_PACKED_TFLOPS = 157.3
 
 
+WORKLOADS = {
+    "mixed2000": {"gen": "config2", "seed": 2000, "B": 1024,
+                  "desc": "mixed hybrid SAT n=2000: 8000 OR (len 3-7), 500 XOR (len 3-20), "
+                          "200 at-least-t (len 10-100), {B} restarts, FP32"},
+    "large": {"gen": "config3", "seed": 3000, "B": 256,
+              "desc": "large hybrid SAT n=100000: 420000 3-SAT, 10000 XOR (len 8-64), 2000 at-least-t "
+                      "(len 128-512; FP64 beyond 256), {B} restarts, FP32"},
+    "large3sat": {"gen": "config3a", "seed": 3000, "B": 256,
+                  "desc": "random 3-SAT n=100000, m=420000 (the 3-SAT part of the large instance), "
+                          "{B} restarts, FP32"},
+}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--seed", type=int, default=2000)
-    ap.add_argument("--restarts", type=int, default=1024)
+    ap.add_argument("--restarts", type=int, default=0, help="restarts (0: the workload's own, 1024 for the default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eta", type=float, default=0.05)
+    ap.add_argument("--workload", default="mixed2000", choices=sorted(WORKLOADS),
+                    help="instance family (the default is the headline configuration)")
     ap.add_argument("--chunk", type=int, default=20,
                     help="iterations per graph replay in the headline loop")
     ap.add_argument("--mode", default="auto", choices=["auto", "per_bin", "group_all", "group_dft"],
@@ -125,9 +140,11 @@ def main():
     from paper_2308_15020_amd import Plan, Problem
 
     dev = torch.device("cuda:0")
-    inst = workloads.config2(args.seed)
-    B = args.restarts
-    x_np = workloads.points(inst.n_vars, B, workloads.point_seed(args.seed))
+    wl = WORKLOADS[args.workload]
+    seed = args.seed if args.workload == "mixed2000" else wl["seed"]
+    inst = getattr(workloads, wl["gen"])(seed)
+    B = args.restarts if args.restarts else wl["B"]
+    x_np = workloads.points(inst.n_vars, B, workloads.point_seed(seed))
     prob = Problem(inst, device=0)
     plan = Plan(prob, B, autotune=not args.no_autotune, tune_cache=args.tune_cache, side_streams=not args.serial,
                 mode=args.mode)
@@ -261,8 +278,7 @@ def main():
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "mixed hybrid SAT n=2000: 8000 OR (len 3-7), 500 XOR (len 3-20), "
-                               "200 at-least-t (len 10-100), 1024 restarts, FP32",
+        "config": {"workload": wl["desc"].format(B=B),
                    "n_vars": inst.n_vars, "n_cons": inst.m, "nnz": inst.nnz, "restarts": B,
                    "step": "objective + gradient + exact round-and-check of x_t (one pass), ERWA weight "
                            "update, projected step",
