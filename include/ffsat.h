@@ -238,6 +238,15 @@ ffsat_status ffsat_erwa_update(ffsat_plan *plan, const int32_t *U, float alpha, 
 ffsat_status ffsat_weight_grad(ffsat_plan *plan, const float *con_val, const float *gF,
                                float *gw, void *stream);
 
+/* Optimisation mode (the paper's MaxSAT-style experiments, where not every
+ * constraint can hold): score[b] = sum of w_c over the constraints that
+ * restart b's rounded point satisfies, from the unsat bits of
+ * ffsat_round_check ([B][ceil(m/32)]).  w: device [m] (e.g. the original
+ * weights; the problem's weights may have been adapted), or NULL for all
+ * ones.  score: device [B] FP64, accumulated in a fixed order. */
+ffsat_status ffsat_sat_weight(ffsat_plan *plan, const uint32_t *unsat_bits, const float *w, double *score,
+                              void *stream);
+
 /* ---- differentiation of the objective (Def. 3) --------------------------- */
 
 /* Vector-Jacobian product of F (per restart) for an upstream gradient gF[B]:

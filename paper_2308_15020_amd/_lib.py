@@ -90,6 +90,7 @@ _SIGS = {
     "ffsat_plan_profile": (I32, [P, I32]),
     "ffsat_plan_profile_read": (I32, [P, I32, C.c_char_p, C.c_size_t]),
     "ffsat_fista": (I32, [P, P, P, P, P, I32, I32, P, P]),
+    "ffsat_sat_weight": (I32, [P, P, P, P, P]),
     "ffsat_run_iters": (I32, [P, P, I32, C.c_float, C.c_float, P, P, P, P]),
     "ffsat_mpnn_create": (I32, [P, P]),
     "ffsat_mpnn_destroy": (I32, [P]),

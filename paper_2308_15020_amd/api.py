@@ -219,6 +219,15 @@ class Plan:
                  _ptr(out.get("unsat_bits")), _ptr(out.get("U")), _stream(dev)))
         return out
 
+    def sat_weight(self, unsat_bits: torch.Tensor, w: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """score[b] = sum of w_c over the constraints restart b satisfies (FP64)."""
+        _need(unsat_bits, (self.B, (self.m + 31) // 32), torch.int32, self.device, "unsat_bits")
+        if w is not None:
+            _need(w, (self.m,), torch.float32, self.device, "w")
+        score = torch.empty(self.B, dtype=torch.float64, device=self.device)
+        check(lib().ffsat_sat_weight(self.handle, _ptr(unsat_bits), _ptr(w), _ptr(score), _stream(self.device)))
+        return score
+
     def erwa_update(self, U: torch.Tensor, alpha: float = 0.4) -> None:
         _need(U, (self.m,), torch.int32, self.device, "U")
         check(lib().ffsat_erwa_update(self.handle, _ptr(U), float(alpha), _stream(self.device)))

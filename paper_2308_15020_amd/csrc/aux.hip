@@ -555,3 +555,38 @@ hipError_t launch_fista_finish(int n, int B, const int32_t *active, float *t, fl
 }
 
 }  // namespace ffsat
+
+// ---------------------------------------------------------------- satisfied weight
+
+namespace ffsat {
+
+// score[b] = sum_c w_c [constraint c holds at restart b's rounded point],
+// from the unsat bits of ffsat_round_check ([B][ceil(m/32)]); w = NULL: all
+// ones.  One wave per restart, FP64 accumulation in constraint order per
+// lane, then a fixed-order wave reduction.
+__global__ __launch_bounds__(256) void k_sat_weight(int m, int B, int wm, const uint32_t *__restrict__ bits,
+                                                    const float *__restrict__ w, double *score)
+{
+    const int b = blockIdx.x * (blockDim.x >> 6) + (int)(threadIdx.x >> 6);
+    if (b >= B) return;
+    const int lane = threadIdx.x & 63;
+    double acc = 0.0;
+    for (int q = lane; q < wm; q += 64) {
+        const uint32_t u = bits[(size_t)b * wm + q];
+        const int c0 = q * 32, c1 = min(m, c0 + 32);
+        for (int c = c0; c < c1; ++c)
+            if (!((u >> (c - c0)) & 1u)) acc += w ? (double)w[c] : 1.0;
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if (lane == 0) score[b] = acc;
+}
+
+hipError_t launch_sat_weight(int m, int B, const uint32_t *bits, const float *w, double *score, hipStream_t s)
+{
+    const int wm = (m + 31) / 32;
+    hipLaunchKernelGGL(k_sat_weight, dim3((B + 3) / 4), dim3(256), 0, s, m, B, wm, bits, w, score);
+    return hipGetLastError();
+}
+
+}  // namespace ffsat

@@ -38,17 +38,19 @@ __device__ __forceinline__ double fmaT<double>(double a, double b, double c) { r
 
 // lane (j - D) / (j + D) inside a group of L lanes; only read where valid.
 // Groups of L <= 16 lanes never straddle a DPP row, so row shifts suffice.
+// bound_ctrl: lanes whose source is outside the row read 0 (never used by
+// the scans, which select on j >= D), so no "old" operand has to be set up
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v)
 {
     const long long u = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(u & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
 template <int D, int L, typename CT>

@@ -1550,6 +1550,14 @@ extern "C" ffsat_status ffsat_round_check_f64(ffsat_plan *pl, const double *x, u
     return FFSAT_OK;
 }
 
+extern "C" ffsat_status ffsat_sat_weight(ffsat_plan *pl, const uint32_t *unsat_bits, const float *w, double *score,
+                                         void *stream)
+{
+    if (!pl || !unsat_bits || !score) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
+    HIPCHK(launch_sat_weight(pl->p->m, pl->B, unsat_bits, w, score, (hipStream_t)stream));
+    return FFSAT_OK;
+}
+
 extern "C" ffsat_status ffsat_erwa_update(ffsat_plan *pl, const int32_t *U, float alpha, void *stream)
 {
     if (!pl || !U) return fail(FFSAT_E_INVALID_ARG, "NULL argument");

@@ -256,6 +256,7 @@ hipError_t launch_nonfinite_f32(int64_t total, const float *x, int32_t *flag, hi
 hipError_t launch_nonfinite_f64(int64_t total, const double *x, int32_t *flag, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_scratch_points(float *x, int64_t total, uint32_t seed, hipStream_t s);
+hipError_t launch_sat_weight(int m, int B, const uint32_t *bits, const float *w, double *score, hipStream_t s);
 int fista_rows(int n, int B);
 hipError_t launch_fista_begin(int B, const float *eta, int32_t *active, int32_t *searching, hipStream_t s);
 hipError_t launch_fista_trial(int n, int B, const float *y, const float *g, const float *eta, const int32_t *searching,

@@ -31,6 +31,7 @@ class SolveResult:
     seconds: float
     best_sat: int
     history: list = field(default_factory=list)
+    best_weight: Optional[float] = None     # optimisation mode: best satisfied weight
 
 
 def _assignment(x: torch.Tensor, b: int) -> np.ndarray:
@@ -41,7 +42,7 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
           alpha: float = 0.4, weighting: bool = True, policy: str = "ROF",
           x0: Optional[torch.Tensor] = None, seed: int = 0, time_limit: Optional[float] = None,
           plan: Optional[Plan] = None, log: bool = False, optimizer: str = "pgd",
-          max_ls: int = 15) -> SolveResult:
+          max_ls: int = 15, maximize: Optional[np.ndarray] = None) -> SolveResult:
     """Alg. 1: returns at the first round in which some restart's rounded point
     satisfies every constraint (decided by the exact checker).
 
@@ -53,6 +54,11 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
     optimizer: 'pgd' (T projected steps of size eta, captured as one graph) or
     'fista' (T accelerated iterations with backtracking from step eta, Alg. 5's
     line search; the state restarts after every rephasing).
+    maximize: optimisation mode (weighted MaxSAT, e.g. Max-Cut as weighted
+    2-XOR): the score of a restart is the sum of these weights over the
+    constraints its rounded point satisfies; the run keeps the best scoring
+    assignment over all rounds and stops early only if every constraint holds.
+    The search itself still uses the problem's (adaptive) weights.
     """
     if optimizer not in ("pgd", "fista"):
         raise ValueError("optimizer must be 'pgd' or 'fista'")
@@ -70,22 +76,31 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
     best = -1
     steps = 0
     state = plan.fista_state(x, eta) if optimizer == "fista" else None
+    w_score = None if maximize is None else torch.as_tensor(np.asarray(maximize, np.float32), device=dev)
+    best_w, best_assign = None, None
     for r in range(rounds):
         if state is None:
             plan.run_steps(x, T, eta)
         else:
             plan.fista(x, state, T, max_ls=max_ls)
         steps += T
-        chk = plan.round_check(x, want=("n_sat", "U"))
+        chk = plan.round_check(x, want=("n_sat", "U") if w_score is None else ("n_sat", "U", "unsat_bits"))
         n_sat = chk["n_sat"]
         b = int(torch.argmax(n_sat).item())
         cur = int(n_sat[b].item())
         best = max(best, cur)
         history.append(cur)
+        if w_score is not None:
+            score = plan.sat_weight(chk["unsat_bits"], w_score)
+            bw = int(torch.argmax(score).item())
+            sw = float(score[bw].item())
+            if best_w is None or sw > best_w:
+                best_w, best_assign = sw, _assignment(x, bw)
         if log:
             print(f"round {r}: best satisfied {cur}/{m}")
         if cur == m:
-            return SolveResult(True, b, _assignment(x, b), r + 1, steps, time.perf_counter() - t_start, m, history)
+            return SolveResult(True, b, _assignment(x, b), r + 1, steps, time.perf_counter() - t_start, m, history,
+                               best_weight=best_w if w_score is None else float(w_score.sum().item()))
         if time_limit is not None and time.perf_counter() - t_start > time_limit:
             break
         if weighting:
@@ -94,4 +109,5 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
         plan.rephase(x, PHASE_MODE[phase], seed=seed * 1000003 + r + 1)
         if state is not None:
             state = plan.fista_state(x, eta)
-    return SolveResult(False, -1, None, len(history), steps, time.perf_counter() - t_start, best, history)
+    return SolveResult(False, -1, best_assign, len(history), steps, time.perf_counter() - t_start, best, history,
+                       best_weight=best_w)

@@ -320,3 +320,46 @@ def planted_hybrid(n: int, seed: int, *, n_or=0, or_len=(3, 3), n_xor=0, xor_len
             ts.append(int(rng.integers(1, max(1, cnt) + 1)))
         groups.append((KIND_CARD, np.array(ts), rows))
     return assemble(n, groups, name=name or f"planted-n{n}"), hidden
+
+
+def maxcut_planted(n: int, seed: int, p_in: float = 0.1, p_out: float = 0.3, w_in: float = 1.0,
+                   w_out: float = 2.0) -> Instance:
+    """Weighted Max-Cut on a planted two-part graph as weighted 2-XOR: edge
+    (u, v) is cut iff exactly one endpoint is True, i.e. XOR(u, v) with odd
+    parity.  Edges appear with probability p_in inside a part and p_out
+    across; weight w_in inside, w_out across (the paper's weighted Max-Cut
+    experiments use MaxSAT-evaluation graphs, which are not available: this
+    generator stands in for them).  meta["part"] holds the planted parts."""
+    rng = np.random.default_rng(seed)
+    part = rng.random(n) < 0.5
+    rows, wts = [], []
+    for u in range(n):
+        for v in range(u + 1, n):
+            same = part[u] == part[v]
+            if rng.random() < (p_in if same else p_out):
+                rows.append(np.array([u + 1, v + 1], np.int32))
+                wts.append(w_in if same else w_out)
+    inst = assemble(n, [(1, np.ones(len(rows), np.int32), rows)], name=f"maxcut_n{n}_s{seed}",
+                    weights=np.asarray(wts, np.float32), meta={"part": part})
+    return inst
+
+
+def parity_learning(n: int, seed: int, m: Optional[int] = None, noise: float = 0.25) -> Instance:
+    """Learning parity with noise as XOR constraints: a hidden secret s in
+    {0,1}^n; m (default 2n) random subsets a (each variable with probability
+    1/2, at least one), each an XOR over a whose parity is <a, s> flipped with
+    probability `noise`.  Not all constraints can hold; the optimum is the
+    assignment satisfying the most.  meta["secret"] (bool, True = True)."""
+    rng = np.random.default_rng(seed)
+    m = 2 * n if m is None else m
+    secret = rng.random(n) < 0.5
+    rows, par = [], []
+    for _ in range(m):
+        a = np.nonzero(rng.random(n) < 0.5)[0]
+        if a.size == 0:
+            a = np.array([rng.integers(0, n)])
+        p = int(secret[a].sum() % 2) ^ int(rng.random() < noise)
+        rows.append((a + 1).astype(np.int32))
+        par.append(p)
+    return assemble(n, [(1, np.asarray(par, np.int32), rows)], name=f"lpn_n{n}_s{seed}",
+                    meta={"secret": secret})
