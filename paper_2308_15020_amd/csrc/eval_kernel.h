@@ -101,11 +101,67 @@ __device__ __forceinline__ void scan_down_cplx(int j, CT &br, CT &bi)
     }
 }
 
+// Lane 15 of each even row broadcast to the following (odd) row; the even
+// rows receive 1.  For 32-lane groups: the lower row's value to the upper.
+__device__ __forceinline__ float bcast15_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(1.0f), __float_as_int(v), 0x142, 0xA, 0xF, false));
+}
+__device__ __forceinline__ double bcast15_f64(double v)
+{
+    const long long u = __double_as_longlong(v);
+    const long long one = __double_as_longlong(1.0);
+    const int lo = __builtin_amdgcn_update_dpp((int)(one & 0xffffffffll), (int)(u & 0xffffffffll), 0x142, 0xA, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(one >> 32), (int)(u >> 32), 0x142, 0xA, 0xF, false);
+    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+template <typename CT>
+__device__ __forceinline__ CT bcast15(CT v)
+{
+    if constexpr (sizeof(CT) == 4) return bcast15_f32(v);
+    else return bcast15_f64(v);
+}
+
+// 32-lane groups: scans inside each 16-lane row with DPP; the lower row's
+// total joins the upper row's prefixes through a row broadcast, and the
+// upper row's total (one lane read) joins the lower row's suffixes.
+template <typename CT>
+__device__ __forceinline__ void group_scan_cplx32(int j, CT tr, CT ti, CT &er, CT &ei, CT &sr, CT &si)
+{
+    const int jr = j & 15;
+    const bool upper = j >= 16;
+    CT ar = tr, ai = ti, br = tr, bi = ti;
+    scan_up_cplx<CT, 16, 1>(jr, ar, ai);      // inclusive prefix inside the row
+    scan_down_cplx<CT, 16, 1>(jr, br, bi);    // inclusive suffix inside the row
+    const CT t0r = bcast15(ar), t0i = bcast15(ai);           // lower row's total (upper rows)
+    const int src = (int)(threadIdx.x & 63 & ~31) | 31;
+    const CT t1r = __shfl(ar, src, 64), t1i = __shfl(ai, src, 64);   // upper row's total
+    // inclusive prefix / suffix over the whole group
+    CT pr = ar, pi = ai, qr = br, qi = bi;
+    if (upper) {
+        pr = fmaT(t0r, ar, -t0i * ai);
+        pi = fmaT(t0r, ai, t0i * ar);
+    } else {
+        qr = fmaT(br, t1r, -bi * t1i);
+        qi = fmaT(br, t1i, bi * t1r);
+    }
+    // exclusive: the neighbour's inclusive value inside the row, the row
+    // totals across the boundary, 1 at the ends
+    const CT xr = from_lower<1, 16>(pr), xi = from_lower<1, 16>(pi);
+    const CT yr = from_upper<1, 16>(qr), yi = from_upper<1, 16>(qi);
+    er = jr > 0 ? xr : (upper ? t0r : CT(1));
+    ei = jr > 0 ? xi : (upper ? t0i : CT(0));
+    sr = jr < 15 ? yr : (upper ? CT(1) : t1r);
+    si = jr < 15 ? yi : (upper ? CT(0) : t1i);
+}
+
 // exclusive prefix (e) and suffix (s) products of the segment totals t
 template <typename CT, int L>
 __device__ __forceinline__ void group_scan_cplx(int j, CT tr, CT ti, CT &er, CT &ei, CT &sr, CT &si)
 {
-    if constexpr (L == 1) {
+    if constexpr (L == 32) {
+        group_scan_cplx32<CT>(j, tr, ti, er, ei, sr, si);
+    } else if constexpr (L == 1) {
         er = 1; ei = 0; sr = 1; si = 0;
     } else {
         CT ar = tr, ai = ti, br = tr, bi = ti;
@@ -139,10 +195,30 @@ __device__ __forceinline__ void scan_down_real(int j, CT &b)
     }
 }
 
+template <typename CT>
+__device__ __forceinline__ void group_scan_real32(int j, CT t, CT &pre, CT &suf)
+{
+    const int jr = j & 15;
+    const bool upper = j >= 16;
+    CT a = t, b = t;
+    scan_up_real<CT, 16, 1>(jr, a);
+    scan_down_real<CT, 16, 1>(jr, b);
+    const CT t0 = bcast15(a);
+    const int src = (int)(threadIdx.x & 63 & ~31) | 31;
+    const CT t1 = __shfl(a, src, 64);
+    const CT p = upper ? t0 * a : a;
+    const CT q = upper ? b : b * t1;
+    const CT x = from_lower<1, 16>(p), y = from_upper<1, 16>(q);
+    pre = jr > 0 ? x : (upper ? t0 : CT(1));
+    suf = jr < 15 ? y : (upper ? CT(1) : t1);
+}
+
 template <typename CT, int L>
 __device__ __forceinline__ void group_scan_real(int j, CT t, CT &pre, CT &suf)
 {
-    if constexpr (L == 1) {
+    if constexpr (L == 32) {
+        group_scan_real32<CT>(j, t, pre, suf);
+    } else if constexpr (L == 1) {
         pre = 1; suf = 1;
     } else {
         CT a = t, b = t;
