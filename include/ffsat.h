@@ -60,6 +60,17 @@ typedef int32_t ffsat_status;
 /* problem flags */
 #define FFSAT_FLAG_FORCE_DFT     1u  /* route OR/XOR through the root-of-unity path too */
 #define FFSAT_FLAG_DEBUG_CHECKS  4u  /* check inputs for NaN/Inf (synchronises) */
+/* Evaluate the root-of-unity constraints in the paper's own unit-circle form
+ * (Alg. 2 with Eq. forward, reduction and inverse as printed: factors
+ * omega^a + l_i, unscaled running products, conjugated Walsh coefficients
+ * f~ = f^ W^-1) instead of the bounded basis.  An ablation: it reproduces on
+ * the device the precision loss the paper reports for long constraints
+ * (Sec. Experiments, the need for high bit precision); the FP64 evaluation
+ * (ffsat_eval_f64, or fp64_min_len = 1) is its intended use.  Same entry
+ * points, outputs and layouts; the grouped launch is not used for these
+ * bins.  Results for long constraints near the corners of the box are
+ * expected to be inaccurate, in FP32 also non-finite. */
+#define FFSAT_FLAG_UNIT_CIRCLE   8u
 
 /* Longest constraint accepted. */
 #define FFSAT_MAX_CONSTRAINT_LEN 512
@@ -357,6 +368,20 @@ ffsat_status ffsat_mpnn_propose(ffsat_plan *plan, const float *mu, float *x, flo
  * this library).  Writes 2*(floor((k+1)/2)+1) doubles (re, im interleaved).
  * Pure host code: no device call. */
 ffsat_status ffsat_coefficients(int32_t kind, int32_t k, int32_t param, double *h_out);
+
+/* Walsh coefficients of one symmetric constraint: f_out[j] = the coefficient
+ * of the elementary symmetric polynomial e_j (j = 0..k) in the constraint's
+ * Walsh expansion (Def. 2, Eq. effi_eval; f = -1 on satisfying inputs,
+ * literal value -1 = True).  Computed exactly in integers (Krawtchouk values)
+ * and rounded once.  Writes k+1 doubles.  Pure host code: no device call. */
+ffsat_status ffsat_walsh_coefficients(int32_t kind, int32_t k, int32_t param, double *f_out);
+
+/* Conjugated Walsh coefficients of the unit-circle form (Eq. inverse):
+ * ft[a] = (1/(k+1)) sum_j fhat_{k-j} omega^(-j a), a = 0..k, omega =
+ * exp(-2 pi i/(k+1)), the ESP sequence ordered e_k .. e_0, so that
+ * WE = sum_a ft[a] prod_i (omega^a + l_i).  Writes 2*(k+1) doubles (re, im
+ * interleaved).  Used by FFSAT_FLAG_UNIT_CIRCLE.  Pure host code. */
+ffsat_status ffsat_unit_circle_coefficients(int32_t kind, int32_t k, int32_t param, double *ft_out);
 
 #ifdef __cplusplus
 }

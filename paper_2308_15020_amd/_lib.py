@@ -22,6 +22,7 @@ STATUS = {
 
 FLAG_FORCE_DFT = 1
 FLAG_DEBUG_CHECKS = 4
+FLAG_UNIT_CIRCLE = 8
 MAX_CONSTRAINT_LEN = 512
 
 
@@ -85,6 +86,8 @@ _SIGS = {
     "ffsat_erwa_update": (I32, [P, P, C.c_float, P]),
     "ffsat_weight_grad": (I32, [P, P, P, P, P]),
     "ffsat_coefficients": (I32, [I32, I32, I32, P]),
+    "ffsat_walsh_coefficients": (I32, [I32, I32, I32, P]),
+    "ffsat_unit_circle_coefficients": (I32, [I32, I32, I32, P]),
     "ffsat_vjp": (I32, [P, P, P, P, P, P, P]),
     "ffsat_rephase": (I32, [P, P, I32, C.c_uint64, P, P]),
     "ffsat_plan_profile": (I32, [P, I32]),

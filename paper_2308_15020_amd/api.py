@@ -324,3 +324,17 @@ def coefficients(kind: int, k: int, param: int) -> np.ndarray:
     buf = np.zeros(2 * na, dtype=np.float64)
     check(lib().ffsat_coefficients(int(kind), int(k), int(param), C.c_void_p(buf.ctypes.data)))
     return buf[0::2] + 1j * buf[1::2]
+
+
+def walsh_coefficients(kind: int, k: int, param: int) -> np.ndarray:
+    """Host-only: Walsh coefficients f^_j of e_j, j = 0..k (exact, rounded once)."""
+    buf = np.zeros(k + 1, dtype=np.float64)
+    check(lib().ffsat_walsh_coefficients(int(kind), int(k), int(param), C.c_void_p(buf.ctypes.data)))
+    return buf
+
+
+def unit_circle_coefficients(kind: int, k: int, param: int) -> np.ndarray:
+    """Host-only: conjugated Walsh coefficients f~[a] of the unit-circle form, a = 0..k (complex)."""
+    buf = np.zeros(2 * (k + 1), dtype=np.float64)
+    check(lib().ffsat_unit_circle_coefficients(int(kind), int(k), int(param), C.c_void_p(buf.ctypes.data)))
+    return buf[0::2] + 1j * buf[1::2]

@@ -241,7 +241,9 @@ __device__ __forceinline__ int group_sum_int(int v)
 // One complex frequency of a constraint: steps i-ii (affine factors psi and
 // their running product), step iii (value term Re(c0 * prod psi)) and the
 // reverse traversal that adds Re(c1 * leave-one-out product) to every
-// position's gradient.  FORM 1: psi = 1 - i tk l; FORM 2: psi = tk - i l.
+// position's gradient.  FORM 1: psi = 1 - i tk l; FORM 2: psi = tk - i l;
+// FORM 3 (the unit-circle form of Eq. forward): psi = (tk + l) + i p0 with
+// (tk, p0) = (cos, sin) of the frequency's root, so that c1 = c0.
 template <typename CT, int SEG, int L, int FORM>
 __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (&gr)[SEG], const FreqT<CT> &fr,
                                           CT &we)
@@ -257,10 +259,15 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
             const CT nr = fmaT(Pi, u, Pr);
             const CT ni = fmaT(-Pr, u, Pi);
             Pr = nr; Pi = ni;
-        } else {
+        } else if constexpr (FORM == 2) {
             const CT l = lv[t];
             const CT nr = fmaT(Pi, l, tk * Pr);
             const CT ni = fmaT(-Pr, l, tk * Pi);
+            Pr = nr; Pi = ni;
+        } else {
+            const CT u = tk + lv[t];
+            const CT nr = fmaT(Pr, u, -Pi * fr.p0);
+            const CT ni = fmaT(Pi, u, Pr * fr.p0);
             Pr = nr; Pi = ni;
         }
     }
@@ -286,10 +293,15 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
                 const CT nr = fmaT(Si, u, Sr);
                 const CT ni = fmaT(-Sr, u, Si);
                 Sr = nr; Si = ni;
-            } else {
+            } else if constexpr (FORM == 2) {
                 const CT l = lv[t];
                 const CT nr = fmaT(Si, l, tkb * Sr);
                 const CT ni = fmaT(-Sr, l, tkb * Si);
+                Sr = nr; Si = ni;
+            } else {
+                const CT u = tkb + lv[t];
+                const CT nr = fmaT(Sr, u, -Si * fr.p0);
+                const CT ni = fmaT(Si, u, Sr * fr.p0);
                 Sr = nr; Si = ni;
             }
         }
@@ -304,8 +316,9 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
 // values through LDS (`lds`: (fg - 1) * (SEG + 1) * 64 values) and wave 0
 // adds them in wave order and writes the results.  Read-only inputs are
 // separate __restrict__ arguments: the compiler may then read uniform
-// descriptors and coefficients through the scalar cache.
-template <typename IO, typename CT, int SEG, int L, bool CPLX>
+// descriptors and coefficients through the scalar cache.  UC: the
+// root-of-unity bins take the unit-circle form (every frequency FORM 3).
+template <typename IO, typename CT, int SEG, int L, bool CPLX, bool UC = false>
 __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, const int unit,
                                           const IO *__restrict__ xin, const ConDesc *__restrict__ con,
                                           const int32_t *__restrict__ lits, const float *__restrict__ wts,
@@ -396,7 +409,17 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
             if constexpr (CPLX) asm volatile("" : "+v"(gr[t]));
         }
         CT we = 0;
-        if constexpr (CPLX) {
+        if constexpr (CPLX && UC) {
+            const int nf = ty.n1;
+            const int f0 = (nf * wg) / fg, f1 = (nf * (wg + 1)) / fg;
+            FreqT<CT> fr = freqs[ty.tab + f0];
+#pragma unroll 1
+            for (int f = f0; f < f1; ++f) {
+                const FreqT<CT> nxt = freqs[ty.tab + f + 1];
+                freq_pass<CT, SEG, L, 3>(j, lv, gr, fr, we);
+                fr = nxt;
+            }
+        } else if constexpr (CPLX) {
             const int n1 = ty.n1, nf = ty.n1 + ty.n2;
             const int f0 = (nf * wg) / fg, f1 = (nf * (wg + 1)) / fg;   // this wave's frequencies
             FreqT<CT> fr = freqs[ty.tab + f0];

@@ -117,6 +117,7 @@ std::vector<cld> conj_coeffs(int kind, int param, int k)
 
 struct FreqD {
     double tk, init, c0re, c0im, c1re, c1im;
+    double p0 = 0.0;   // form 3: imaginary part of the root
 };
 
 struct TypeD {
@@ -189,6 +190,232 @@ TypeD dft_type(const std::vector<cld> &hv, int k, int L, int s)
     return t;
 }
 
+// ---- the unit-circle form (ablation of the basis above)
+
+// Signed integers of any size, with just the operations the Krawtchouk
+// recurrences below need: multiply by a small integer, add, exact division
+// by a small integer, conversion to long double.
+struct BigInt {
+    int sign = 0;                  // -1, 0, +1
+    std::vector<uint32_t> mag;     // little-endian base 2^32, no leading zero limb
+
+    static BigInt of(long long v)
+    {
+        BigInt r;
+        if (v == 0) return r;
+        r.sign = v < 0 ? -1 : 1;
+        unsigned long long u = v < 0 ? 0ULL - (unsigned long long)v : (unsigned long long)v;
+        while (u) { r.mag.push_back((uint32_t)u); u >>= 32; }
+        return r;
+    }
+    void trim()
+    {
+        while (!mag.empty() && mag.back() == 0) mag.pop_back();
+        if (mag.empty()) sign = 0;
+    }
+    BigInt mul(long long m) const
+    {
+        BigInt r;
+        if (sign == 0 || m == 0) return r;
+        const unsigned long long um = m < 0 ? 0ULL - (unsigned long long)m : (unsigned long long)m;
+        r.sign = (m < 0) ? -sign : sign;
+        r.mag.assign(mag.size() + 2, 0u);
+        for (int part = 0; part < 2; ++part) {   // um < 2^64: two 32-bit halves
+            const uint64_t mm = (uint32_t)(um >> (32 * part));
+            uint64_t carry = 0;
+            for (size_t i = 0; i < mag.size(); ++i) {
+                const uint64_t t = (uint64_t)mag[i] * mm + r.mag[i + part] + carry;
+                r.mag[i + part] = (uint32_t)t;
+                carry = t >> 32;
+            }
+            for (size_t i = mag.size() + part; carry; ++i) {
+                const uint64_t t = (uint64_t)r.mag[i] + carry;
+                r.mag[i] = (uint32_t)t;
+                carry = t >> 32;
+            }
+        }
+        r.trim();
+        return r;
+    }
+    static int cmp_mag(const BigInt &a, const BigInt &b)
+    {
+        if (a.mag.size() != b.mag.size()) return a.mag.size() < b.mag.size() ? -1 : 1;
+        for (size_t i = a.mag.size(); i-- > 0;)
+            if (a.mag[i] != b.mag[i]) return a.mag[i] < b.mag[i] ? -1 : 1;
+        return 0;
+    }
+    BigInt add(const BigInt &b) const
+    {
+        if (b.sign == 0) return *this;
+        if (sign == 0) return b;
+        BigInt r;
+        if (sign == b.sign) {
+            r.sign = sign;
+            r.mag.assign(std::max(mag.size(), b.mag.size()) + 1, 0u);
+            uint64_t carry = 0;
+            for (size_t i = 0; i < r.mag.size(); ++i) {
+                const uint64_t t = (uint64_t)(i < mag.size() ? mag[i] : 0u) + (i < b.mag.size() ? b.mag[i] : 0u) + carry;
+                r.mag[i] = (uint32_t)t;
+                carry = t >> 32;
+            }
+        } else {
+            const int c = cmp_mag(*this, b);
+            if (c == 0) return r;
+            const BigInt &hi = c > 0 ? *this : b, &lo = c > 0 ? b : *this;
+            r.sign = hi.sign;
+            r.mag.assign(hi.mag.size(), 0u);
+            int64_t borrow = 0;
+            for (size_t i = 0; i < hi.mag.size(); ++i) {
+                int64_t t = (int64_t)hi.mag[i] - (i < lo.mag.size() ? lo.mag[i] : 0u) - borrow;
+                borrow = t < 0 ? 1 : 0;
+                r.mag[i] = (uint32_t)(t + (borrow << 32));
+            }
+        }
+        r.trim();
+        return r;
+    }
+    BigInt neg() const { BigInt r = *this; r.sign = -r.sign; return r; }
+    // exact division by d > 0 (the caller guarantees divisibility)
+    BigInt div_exact(uint32_t d) const
+    {
+        BigInt r = *this;
+        uint64_t rem = 0;
+        for (size_t i = r.mag.size(); i-- > 0;) {
+            const uint64_t cur = (rem << 32) | r.mag[i];
+            r.mag[i] = (uint32_t)(cur / d);
+            rem = cur % d;
+        }
+        r.trim();
+        return r;
+    }
+    long double to_ld() const
+    {
+        long double v = 0.0L;
+        for (size_t i = mag.size(); i-- > 0;) v = v * 4294967296.0L + (long double)mag[i];
+        return sign < 0 ? -v : v;
+    }
+};
+
+// Walsh coefficients fhat[j] of a symmetric constraint: the coefficient of
+// the elementary symmetric polynomial e_j in its Walsh expansion (Def. 2 and
+// Eq. effi_eval), j = 0..k, f = -1 on satisfying count vectors.  Exact up to
+// the final rounding:
+//   XOR with parity p: only e_k, with coefficient 2p - 1;
+//   at least t (OR: t = 1), 1 <= t <= k: fhat_0 = 1 - 2^(1-k) sum_{c>=t} C(k,c)
+//     and, for j >= 1, fhat_j = 2^(1-k) K_{t-1}(j-1; k-1), a binary Krawtchouk
+//     value (the derivative of the tail sum of the Krawtchouk generating
+//     function (1-z)^c (1+z)^(k-c) over c >= t telescopes to one term).
+//     With K = k-1, n = t-1: D_x = C(K,x) K_n(x) = C(K,n) K_x(n) satisfies
+//     (x+1) D_{x+1} = (K-2n) D_x - (K-x+1) D_{x-1}, D_0 = C(K,n),
+//     D_1 = (K-2n) C(K,n), all integers; fhat_j = 2^(1-k) D_{j-1} / C(K,j-1).
+//   t <= 0 or t > k: constant -1 or +1.
+std::vector<long double> walsh_exact(int kind, int param, int k)
+{
+    std::vector<long double> fh((size_t)k + 1, 0.0L);
+    if (kind == FFSAT_KIND_XOR) {
+        fh[(size_t)k] = (param & 1) ? 1.0L : -1.0L;
+        return fh;
+    }
+    const int t = kind == FFSAT_KIND_OR ? 1 : param;
+    if (t <= 0) { fh[0] = -1.0L; return fh; }
+    if (t > k) { fh[0] = 1.0L; return fh; }
+    // binomials C(k, c) and the tail sum
+    BigInt C = BigInt::of(1), tail;
+    for (int c = 0; c <= k; ++c) {
+        if (c >= t) tail = tail.add(C);
+        if (c < k) C = C.mul(k - c).div_exact((uint32_t)(c + 1));
+    }
+    // fhat_0 = (2^k - 2 tail) / 2^k
+    BigInt two_k = BigInt::of(1);
+    for (int i = 0; i < k; ++i) two_k = two_k.mul(2);
+    fh[0] = ldexpl(two_k.add(tail.mul(-2)).to_ld(), -k);
+    const int K = k - 1, n = t - 1;
+    BigInt CKn = BigInt::of(1);
+    for (int i = 0; i < n; ++i) CKn = CKn.mul(K - i).div_exact((uint32_t)(i + 1));
+    BigInt Dm1, D = CKn, CKx = BigInt::of(1);   // D_{x-1}, D_x, C(K, x)
+    for (int x = 0; x <= K; ++x) {
+        fh[(size_t)x + 1] = ldexpl(D.to_ld() / CKx.to_ld(), 1 - k);
+        if (x == K) break;
+        BigInt Dn = (x == 0) ? CKn.mul(K - 2 * n)
+                             : D.mul(K - 2 * n).add(Dm1.mul(-(long long)(K - x + 1))).div_exact((uint32_t)(x + 1));
+        Dm1 = D;
+        D = Dn;
+        CKx = CKx.mul(K - x).div_exact((uint32_t)(x + 1));
+    }
+    return fh;
+}
+
+// Conjugated Walsh coefficients of the unit-circle form, f~ = f^ W^-1
+// (Eq. inverse): with the ESP sequence ordered e_k .. e_0 (the order the
+// convolution of [l_i, 1] produces), omega = exp(-2 pi i / N), N = k + 1,
+//   f~[a] = (1/N) sum_j fhat_{k-j} omega^(-j a),  a = 0..k,
+// so that WE = sum_a f~[a] prod_i (omega^a + l_i).  Angles are reduced
+// exactly in integers; arithmetic in long double.
+std::vector<cld> uc_coeffs(int kind, int param, int k)
+{
+    const std::vector<long double> fh = walsh_exact(kind, param, k);
+    const long long N = k + 1;
+    std::vector<cld> roots((size_t)N);
+    for (long long r = 0; r < N; ++r) {
+        const long double ang = 2.0L * PI_L * (long double)r / (long double)N;   // omega^(-r)
+        roots[(size_t)r] = cld(cosl(ang), sinl(ang));
+    }
+    std::vector<cld> ft((size_t)N);
+    for (long long a = 0; a < N; ++a) {
+        cld acc = 0.0L;
+        for (long long j = 0; j <= k; ++j) {
+            const long double f = fh[(size_t)(k - j)];
+            if (f != 0.0L) acc += f * roots[(size_t)((j * a) % N)];
+        }
+        ft[(size_t)a] = acc / (long double)N;
+    }
+    return ft;
+}
+
+// Kernel tables of the unit-circle form.  Frequency a = 0 (omega^0 = 1) is
+// the real chain prod (1 + l); a = 1..ceil(k/2)-1 are complex (weight 2 by
+// conjugate symmetry, f~[N-a] = conj f~[a]); for odd k, a = N/2 is the factor
+// l - 1, taken as a complex entry with zero imaginary part.  Padding literals
+// hold 0: factor 1 in the real chain and omega^a elsewhere, divided out of
+// the coefficients.  Running products start at 1 (no rescaling, as printed).
+TypeD uc_type(const std::vector<cld> &ft, int k, int L, int s)
+{
+    TypeD t;
+    t.cls = CLASS_DFT;
+    const long long N = k + 1;
+    const long long npad = (long long)L * s - k;
+    t.cst = 0.0;
+    t.pad = 0.0;
+    t.has_real = 1;
+    t.alpha = 1.0;
+    t.beta = 1.0;
+    t.c0r = t.c1r = (double)ft[0].real();
+    for (long long a = 1; 2 * a <= N; ++a) {
+        const bool mid = 2 * a == N;
+        const long double th = 2.0L * PI_L * (long double)a / (long double)N;
+        const long double cr = mid ? -1.0L : cosl(th), si = mid ? 0.0L : -sinl(th);   // omega^a
+        const long long r = (a * npad) % N;   // divide by omega^(a npad)
+        const long double ph = 2.0L * PI_L * (long double)r / (long double)N;
+        const cld corr = mid ? cld((npad & 1) ? -1.0L : 1.0L, 0.0L) : cld(cosl(ph), sinl(ph));
+        const cld c0 = (mid ? 1.0L : 2.0L) * ft[(size_t)a] * corr;
+        FreqD fd{(double)cr, 1.0, (double)c0.real(), (double)c0.imag(), (double)c0.real(), (double)c0.imag()};
+        fd.p0 = (double)si;
+        t.fr.push_back(fd);
+    }
+    t.n1 = (int)t.fr.size();
+    t.n2 = 0;
+    return t;
+}
+
+// Segment shape of a unit-circle bin: L = 1 with SEG in {4, 8, 16}, else
+// SEG = 16 and the smallest L in 2..32 with 16 L >= k.
+void shape_for_uc(int k, int &seg, int &L)
+{
+    L = 1;
+    while (16 * L < k) L <<= 1;
+    seg = L > 1 ? 16 : (k <= 4 ? 4 : (k <= 8 ? 8 : 16));
+}
+
 // Segment shape of a constraint of length k: L lanes (a power of two) of SEG
 // positions each (4, 8, 16 or 24 for FP32 arithmetic, 32 past k = 384;
 // 4, 8, 12 or 16 for FP64), L * SEG >= k, the smallest such L and then the
@@ -245,6 +472,29 @@ extern "C" ffsat_status ffsat_coefficients(int32_t kind, int32_t k, int32_t para
     for (int a = 0; a <= (k + 1) / 2; ++a) {
         h_out[2 * a] = (double)h[(size_t)a].real();
         h_out[2 * a + 1] = (double)h[(size_t)a].imag();
+    }
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_walsh_coefficients(int32_t kind, int32_t k, int32_t param, double *f_out)
+{
+    if (!f_out || k < 1 || k > FFSAT_MAX_CONSTRAINT_LEN)
+        return fail(FFSAT_E_INVALID_ARG, "ffsat_walsh_coefficients: bad argument");
+    if (kind < 0 || kind > 2) return fail(FFSAT_E_BAD_KIND, "ffsat_walsh_coefficients: bad kind %d", kind);
+    const std::vector<long double> f = walsh_exact(kind, param, k);
+    for (int j = 0; j <= k; ++j) f_out[j] = (double)f[(size_t)j];
+    return FFSAT_OK;
+}
+
+extern "C" ffsat_status ffsat_unit_circle_coefficients(int32_t kind, int32_t k, int32_t param, double *ft_out)
+{
+    if (!ft_out || k < 1 || k > FFSAT_MAX_CONSTRAINT_LEN)
+        return fail(FFSAT_E_INVALID_ARG, "ffsat_unit_circle_coefficients: bad argument");
+    if (kind < 0 || kind > 2) return fail(FFSAT_E_BAD_KIND, "ffsat_unit_circle_coefficients: bad kind %d", kind);
+    const std::vector<cld> ft = uc_coeffs(kind, param, k);
+    for (int a = 0; a <= k; ++a) {
+        ft_out[2 * a] = (double)ft[(size_t)a].real();
+        ft_out[2 * a + 1] = (double)ft[(size_t)a].imag();
     }
     return FFSAT_OK;
 }
@@ -316,6 +566,7 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
     Ly.io = io;
     const int m = p->m, n = p->n;
     const bool force_dft = (p->flags & FFSAT_FLAG_FORCE_DFT) != 0;
+    const bool uc = (p->flags & FFSAT_FLAG_UNIT_CIRCLE) != 0;
 
     // 1. classify every constraint into a (type, bin)
     std::map<TypeKey, int> type_index;
@@ -343,8 +594,9 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
         if (io == IO_F64) ct = CT_F64;
         else ct = (cls == CLASS_DFT && k >= p->fp64_min_len) ? CT_F64 : CT_F32;
         int seg, L;
-        shape_for(ct, k, seg, L);
-        if (!eval_variant_exists(io, ct, cls, seg, L))
+        if (uc && cls == CLASS_DFT) shape_for_uc(k, seg, L);
+        else shape_for(ct, k, seg, L);
+        if (!eval_variant_exists(io, ct, cls, seg, L, uc))
             return fail(FFSAT_E_UNSUPPORTED, "no kernel variant for constraint %d (k=%d)", c, k);
         TypeKey tk;
         if (cls == CLASS_REAL) tk = TypeKey{cls, ct, rk, rparam, 0, 0, 0};
@@ -359,8 +611,9 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
             if (cls == CLASS_DFT) {
                 auto key = std::make_tuple(tk.kind, tk.param, k);
                 auto mh = memo.find(key);
-                if (mh == memo.end()) mh = memo.emplace(key, conj_coeffs(tk.kind, tk.param, k)).first;
-                td = dft_type(mh->second, k, L, seg);
+                if (mh == memo.end())
+                    mh = memo.emplace(key, uc ? uc_coeffs(tk.kind, tk.param, k) : conj_coeffs(tk.kind, tk.param, k)).first;
+                td = uc ? uc_type(mh->second, k, L, seg) : dft_type(mh->second, k, L, seg);
             }
             else if (rk == RK_OR) td = real_or();
             else if (rk == RK_XOR) td = real_xor(rparam);
@@ -378,6 +631,7 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
         if (bi == bin_index.end()) {
             Bin b;
             b.cls = cls; b.ct = ct; b.seg = seg; b.L = L;
+            b.uc = uc && cls == CLASS_DFT;
             bidx = (int)bins.size();
             bins.push_back(b);
             bin_index[bk] = bidx;
@@ -471,8 +725,8 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
         t64.push_back(b);
         for (const FreqD &f : td.fr) {
             f32.push_back(FreqF32{(float)f.tk, (float)f.init, (float)f.c0re, (float)f.c0im,
-                                  (float)f.c1re, (float)f.c1im, 0.f, 0.f});
-            f64.push_back(FreqF64{f.tk, f.init, f.c0re, f.c0im, f.c1re, f.c1im, 0.0, 0.0});
+                                  (float)f.c1re, (float)f.c1im, (float)f.p0, 0.f});
+            f64.push_back(FreqF64{f.tk, f.init, f.c0re, f.c0im, f.c1re, f.c1im, f.p0, 0.0});
         }
     }
     // one entry of padding: the kernels prefetch the entry after a type's last
@@ -621,8 +875,8 @@ static ffsat_status ensure_workspace(ffsat_plan *pl, int io)
 static std::string bin_key(const ffsat_plan *pl, const Bin &b, int io)
 {
     char buf[256];
-    snprintf(buf, sizeof buf, "gfx950|io%d|B%d|c%d|t%d|s%d|L%d|n%d|l%lld|k%d", io, pl->B, b.cls, b.ct, b.seg,
-             b.L, b.count, (long long)b.lits, b.maxk);
+    snprintf(buf, sizeof buf, "gfx950|io%d|B%d|c%d%s|t%d|s%d|L%d|n%d|l%lld|k%d", io, pl->B, b.cls, b.uc ? "uc" : "",
+             b.ct, b.seg, b.L, b.count, (long long)b.lits, b.maxk);
     return buf;
 }
 
@@ -754,7 +1008,7 @@ static ffsat_status build_groups(ffsat_plan *pl)
     int row0 = 0;
     for (int i = 0; i < (int)bins.size(); ++i) {
         const Bin &b = bins[i];
-        const int v = group_variant(b.ct, b.cls, b.seg, b.L);
+        const int v = b.uc ? -1 : group_variant(b.ct, b.cls, b.seg, b.L);
         const int fg = b.cls == CLASS_DFT ? b.fg : 1;
         const int rows = (b.count + b.cpw - 1) / b.cpw;
         if (v < 0 || (fg != 1 && fg != 4) || (pl->mode == MODE_GROUP_DFT && b.cls != CLASS_DFT)) {
@@ -1268,7 +1522,7 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
         o << (io ? ", " : "") << "\"" << (io ? "f64" : "f32") << "\": [";
         for (size_t i = 0; i < pl->bins[io].size(); ++i) {
             const Bin &b = pl->bins[io][i];
-            o << (i ? ", " : "") << "{\"class\": \"" << (b.cls == CLASS_DFT ? "dft" : "real") << "\", \"ct\": \""
+            o << (i ? ", " : "") << "{\"class\": \"" << (b.cls == CLASS_DFT ? (b.uc ? "dft_uc" : "dft") : "real") << "\", \"ct\": \""
               << (b.ct == CT_F32 ? "f32" : "f64") << "\", \"seg\": " << b.seg << ", \"L\": " << b.L
               << ", \"first\": " << b.first << ", \"count\": " << b.count << ", \"maxk\": " << b.maxk
               << ", \"lits\": " << b.lits << ", \"cost\": " << b.cost << ", \"flops_per_restart\": " << b.flops

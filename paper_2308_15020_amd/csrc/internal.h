@@ -64,6 +64,7 @@ struct Bin {
     double exec_pos = 0;        // literal positions executed per restart (with padding)
     int cpw = 1, wpb = 4;       // tile shape: constraints per wave, waves per block
     int fg = 1;                 // root-of-unity bins: waves splitting one unit's frequencies
+    bool uc = false;            // root-of-unity bin in the unit-circle form (ablation)
 };
 
 struct ProfRec {
@@ -216,7 +217,7 @@ hipError_t launch_eval_bin_f64(const Bin &bin, const EvalArgs<double> &a, hipStr
 int group_variant(int ct, int cls, int seg, int L);
 hipError_t launch_eval_group_f32(const EvalArgs<float> &a, const GroupEntry *ent, const int2 *blk, int nblk,
                                  size_t lds, hipStream_t s);
-bool eval_variant_exists(int io, int ct, int cls, int seg, int L);
+bool eval_variant_exists(int io, int ct, int cls, int seg, int L, bool uc);
 
 // Reduction after the evaluation kernels: gradient (or fused projected step
 // when x_step != null) over the variable-major transpose, objective rows into
