@@ -38,6 +38,69 @@ def _assignment(x: torch.Tensor, b: int) -> np.ndarray:
     return (x[:, b] < 0).cpu().numpy()
 
 
+class Search:
+    """One arm of the search: a plan of B restarts with its own weights (held
+    by its problem), rephasing policy and optimiser.  `run_round` does T
+    steps and the exact check; `adapt` applies ERWA and the next phase."""
+
+    def __init__(self, problem: Problem, B: int, T: int = 50, eta: float = 0.05, alpha: float = 0.4,
+                 weighting: bool = True, policy: str = "ROF", x0: Optional[torch.Tensor] = None, seed: int = 0,
+                 plan: Optional[Plan] = None, optimizer: str = "pgd", max_ls: int = 15,
+                 maximize: Optional[np.ndarray] = None):
+        if optimizer not in ("pgd", "fista"):
+            raise ValueError("optimizer must be 'pgd' or 'fista'")
+        if not policy or any(ph not in PHASE_MODE for ph in policy):
+            raise ValueError("policy must be a non-empty string over 'O', 'F', 'R'")
+        self.problem, self.B, self.T, self.eta, self.alpha = problem, B, T, eta, alpha
+        self.weighting, self.policy, self.seed, self.max_ls = weighting, policy, seed, max_ls
+        dev = problem.device
+        self.plan = plan or Plan(problem, B)
+        problem.set_weights(np.ones(problem.m, dtype=np.float32))
+        if x0 is None:
+            self.x = torch.empty(problem.n, B, dtype=torch.float32, device=dev)
+            self.plan.rephase(self.x, PHASE_MODE["R"], seed=seed)
+        else:
+            self.x = x0.detach().to(dev, torch.float32).contiguous().clone()
+        self.state = self.plan.fista_state(self.x, eta) if optimizer == "fista" else None
+        self.w_score = None if maximize is None else torch.as_tensor(np.asarray(maximize, np.float32), device=dev)
+        self.best_w, self.best_assign = None, None
+        self.steps = 0
+        self.history = []
+        self._chk = None
+
+    def run_round(self):
+        """T steps, then the exact check of the rounded points.  Returns
+        (best restart, its satisfied count)."""
+        if self.state is None:
+            self.plan.run_steps(self.x, self.T, self.eta)
+        else:
+            self.plan.fista(self.x, self.state, self.T, max_ls=self.max_ls)
+        self.steps += self.T
+        want = ("n_sat", "U") if self.w_score is None else ("n_sat", "U", "unsat_bits")
+        chk = self.plan.round_check(self.x, want=want)
+        self._chk = chk
+        b = int(torch.argmax(chk["n_sat"]).item())
+        cur = int(chk["n_sat"][b].item())
+        self.history.append(cur)
+        if self.w_score is not None:
+            score = self.plan.sat_weight(chk["unsat_bits"], self.w_score)
+            bw = int(torch.argmax(score).item())
+            sw = float(score[bw].item())
+            if self.best_w is None or sw > self.best_w:
+                self.best_w, self.best_assign = sw, _assignment(self.x, bw)
+        return b, cur
+
+    def adapt(self, r: int):
+        """After failed round r: ERWA on this round's counts, then the phase
+        policy[r mod len(policy)] for every restart."""
+        if self.weighting:
+            self.plan.erwa_update(self._chk["U"], self.alpha)
+        phase = self.policy[r % len(self.policy)]
+        self.plan.rephase(self.x, PHASE_MODE[phase], seed=self.seed * 1000003 + r + 1)
+        if self.state is not None:
+            self.state = self.plan.fista_state(self.x, self.eta)
+
+
 def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: float = 0.05,
           alpha: float = 0.4, weighting: bool = True, policy: str = "ROF",
           x0: Optional[torch.Tensor] = None, seed: int = 0, time_limit: Optional[float] = None,
@@ -60,54 +123,72 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
     assignment over all rounds and stops early only if every constraint holds.
     The search itself still uses the problem's (adaptive) weights.
     """
-    if optimizer not in ("pgd", "fista"):
-        raise ValueError("optimizer must be 'pgd' or 'fista'")
     t_start = time.perf_counter()
-    dev = problem.device
-    plan = plan or Plan(problem, B)
     m = problem.m
-    problem.set_weights(np.ones(m, dtype=np.float32))
-    if x0 is None:
-        x = torch.empty(problem.n, B, dtype=torch.float32, device=dev)
-        plan.rephase(x, PHASE_MODE["R"], seed=seed)
-    else:
-        x = x0.detach().to(dev, torch.float32).contiguous().clone()
-    history = []
+    S = Search(problem, B, T=T, eta=eta, alpha=alpha, weighting=weighting, policy=policy, x0=x0, seed=seed,
+               plan=plan, optimizer=optimizer, max_ls=max_ls, maximize=maximize)
     best = -1
-    steps = 0
-    state = plan.fista_state(x, eta) if optimizer == "fista" else None
-    w_score = None if maximize is None else torch.as_tensor(np.asarray(maximize, np.float32), device=dev)
-    best_w, best_assign = None, None
     for r in range(rounds):
-        if state is None:
-            plan.run_steps(x, T, eta)
-        else:
-            plan.fista(x, state, T, max_ls=max_ls)
-        steps += T
-        chk = plan.round_check(x, want=("n_sat", "U") if w_score is None else ("n_sat", "U", "unsat_bits"))
-        n_sat = chk["n_sat"]
-        b = int(torch.argmax(n_sat).item())
-        cur = int(n_sat[b].item())
+        b, cur = S.run_round()
         best = max(best, cur)
-        history.append(cur)
-        if w_score is not None:
-            score = plan.sat_weight(chk["unsat_bits"], w_score)
-            bw = int(torch.argmax(score).item())
-            sw = float(score[bw].item())
-            if best_w is None or sw > best_w:
-                best_w, best_assign = sw, _assignment(x, bw)
         if log:
             print(f"round {r}: best satisfied {cur}/{m}")
         if cur == m:
-            return SolveResult(True, b, _assignment(x, b), r + 1, steps, time.perf_counter() - t_start, m, history,
-                               best_weight=best_w if w_score is None else float(w_score.sum().item()))
+            return SolveResult(True, b, _assignment(S.x, b), r + 1, S.steps, time.perf_counter() - t_start, m,
+                               S.history, best_weight=S.best_w if S.w_score is None else float(S.w_score.sum().item()))
         if time_limit is not None and time.perf_counter() - t_start > time_limit:
             break
-        if weighting:
-            plan.erwa_update(chk["U"], alpha)
-        phase = policy[r % len(policy)]
-        plan.rephase(x, PHASE_MODE[phase], seed=seed * 1000003 + r + 1)
-        if state is not None:
-            state = plan.fista_state(x, eta)
-    return SolveResult(False, -1, best_assign, len(history), steps, time.perf_counter() - t_start, best, history,
-                       best_weight=best_w)
+        S.adapt(r)
+    return SolveResult(False, -1, S.best_assign, len(S.history), S.steps, time.perf_counter() - t_start, best,
+                       S.history, best_weight=S.best_w)
+
+
+@dataclass
+class Arm:
+    """One strategy of a portfolio: its share of the restarts and its heuristics."""
+    B: int
+    weighting: bool = True
+    policy: str = "ROF"
+    eta: float = 0.05
+    optimizer: str = "pgd"
+    alpha: float = 0.4
+
+
+def solve_portfolio(inst, arms, rounds: int = 100, T: int = 50, seed: int = 0, device: int = 0,
+                    problems=None, log: bool = False) -> SolveResult:
+    """Several strategies side by side on one GPU (Table 2's portfolio; the
+    paper runs its arms on separate GPUs).  Each arm has its own problem
+    object (its own adaptive weights) and restarts; every round runs T steps
+    of each arm, and the run stops at the first round in which any arm's
+    rounded point satisfies everything.  `restart` of the result indexes the
+    arms' restarts in order (arm 0's first).  problems: reuse one Problem per
+    arm (their weights are reset)."""
+    t_start = time.perf_counter()
+    probs = problems if problems is not None else [Problem(inst, device=device) for _ in arms]
+    if len(probs) != len(arms):
+        raise ValueError("one problem per arm")
+    m = probs[0].m
+    searches = [Search(p, a.B, T=T, eta=a.eta, alpha=a.alpha, weighting=a.weighting, policy=a.policy,
+                       seed=seed * 7919 + i, optimizer=a.optimizer) for i, (p, a) in enumerate(zip(probs, arms))]
+    offs = np.cumsum([0] + [a.B for a in arms])
+    best, history = -1, []
+    for r in range(rounds):
+        cur_best, hit = -1, None
+        for i, S in enumerate(searches):
+            b, cur = S.run_round()
+            if cur > cur_best:
+                cur_best = cur
+            if cur == m and hit is None:
+                hit = (i, b)
+        best = max(best, cur_best)
+        history.append(cur_best)
+        if log:
+            print(f"round {r}: best satisfied {cur_best}/{m}")
+        if hit is not None:
+            i, b = hit
+            return SolveResult(True, int(offs[i] + b), _assignment(searches[i].x, b), r + 1,
+                               sum(S.steps for S in searches), time.perf_counter() - t_start, m, history)
+        for S in searches:
+            S.adapt(r)
+    return SolveResult(False, -1, None, len(history), sum(S.steps for S in searches),
+                       time.perf_counter() - t_start, best, history)

@@ -134,3 +134,34 @@ def test_time_to_solve_harness_runs(ffs):
     assert s["instances"] == 2
     assert 0.0 <= s["solve_rate"]["uniform"] <= 1.0 and 0.0 <= s["solve_rate"]["learned"] <= 1.0
     assert np.isfinite(s["train_loss"]).all()
+
+
+def test_portfolio_arms_keep_their_own_weights(ffs):
+    """Two strategies side by side: the run stops when either arm satisfies
+    everything (checked by the oracle), the weighting arm's problem has adapted
+    weights and the fixed arm's problem keeps unit weights."""
+    from paper_2308_15020_amd.solver import Arm, solve_portfolio
+    inst, _ = workloads.planted_hybrid(300, 12, n_or=1150, or_len=(3, 3))
+    probs = [ffs.Problem(inst, device=0), ffs.Problem(inst, device=0)]
+    arms = [Arm(128, weighting=False, policy="R", eta=0.1), Arm(128, weighting=True, policy="ROF", eta=0.1)]
+    res = solve_portfolio(inst, arms, rounds=60, T=40, seed=3, problems=probs)
+    print(res.solved, res.rounds, res.restart, res.best_sat, inst.m)
+    assert res.solved and 0 <= res.restart < 256
+    x = np.where(res.assignment, -1.0, 1.0)[:, None]
+    assert int(oracle.check(inst, x)["n_sat"][0]) == inst.m
+    w0, w1 = probs[0].get_weights().cpu().numpy(), probs[1].get_weights().cpu().numpy()
+    assert np.all(w0 == 1.0)
+    if res.rounds > 1:
+        assert not np.all(w1 == 1.0)
+
+
+def test_table2_harness_runs(ffs):
+    """The restart-heuristics table end to end on a tiny budget."""
+    from paper_2308_15020_amd import heuristics
+    import argparse
+    t = heuristics.run(argparse.Namespace(n=[20], instances=2, B=64, rounds=3, T=20, eta=0.1))
+    s = t[20]
+    assert s["instances"] == 2
+    for arm in ("plain", "heuristic", "portfolio", "two_device"):
+        assert 0 <= s[arm]["solved"] <= 2 and 1 <= s[arm]["par2_iters"] <= 6
+    assert s["two_device"]["solved"] >= max(s["plain"]["solved"], s["heuristic"]["solved"])

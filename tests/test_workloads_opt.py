@@ -26,3 +26,21 @@ def test_parity_learning_labels():
         agree.append(int(s[v].sum() % 2) == inst.params[c])
     frac_flipped = 1.0 - np.mean(agree)
     assert abs(frac_flipped - 0.25) < 0.03
+
+
+def test_hidden2_ksat_is_satisfied_by_both_hidden_assignments():
+    import oracle
+    inst, sigma = workloads.hidden2_ksat(120, 5)
+    assert inst.m == round(4.26 * 120) and np.all(np.diff(inst.con_ptr) == 3)
+    for a in (sigma, ~sigma):
+        x = np.where(a, -1.0, 1.0)[:, None]
+        assert int(oracle.check(inst, x)["n_sat"][0]) == inst.m
+    # no polarity bias: positive and negative occurrences balance overall
+    pos = int((inst.lits > 0).sum())
+    assert abs(pos - inst.nnz / 2) < 4 * np.sqrt(inst.nnz)
+    # and the majority polarity of a variable does not reveal sigma
+    v = np.abs(inst.lits) - 1
+    net = np.bincount(v, weights=np.sign(inst.lits), minlength=inst.n_vars)
+    lean_true = net < 0          # more negative occurrences: x < 0 is True
+    agree = np.mean(lean_true[net != 0] == sigma[net != 0])
+    assert 0.3 < agree < 0.7

@@ -322,6 +322,28 @@ def planted_hybrid(n: int, seed: int, *, n_or=0, or_len=(3, 3), n_xor=0, xor_len
     return assemble(n, groups, name=name or f"planted-n{n}"), hidden
 
 
+def hidden2_ksat(n: int, seed: int, ratio: float = 4.26, k: int = 3, name="") -> tuple:
+    """Satisfiable random k-SAT with two hidden assignments (sigma and its
+    complement), the "2-hidden" generator of Achlioptas, Jia and Moore (2005):
+    clauses over k distinct variables with Bernoulli(1/2) signs are drawn
+    uniformly and kept only if both sigma and not-sigma satisfy them (at least
+    one literal true and one false under sigma).  Every variable then occurs
+    as often positive as negative in expectation, so, unlike a one-sided
+    planted formula, the literal counts say nothing about sigma.
+    m = round(ratio * n).  Returns (Instance, sigma bool[n], True = True)."""
+    rng = np.random.default_rng(seed)
+    sigma = rng.random(n) < 0.5
+    m = int(round(ratio * n))
+    rows = []
+    while len(rows) < m:
+        v = rng.choice(n, size=k, replace=False)
+        neg = rng.random(k) < 0.5
+        true_under_sigma = np.where(neg, ~sigma[v], sigma[v])
+        if true_under_sigma.any() and not true_under_sigma.all():
+            rows.append(np.where(neg, -(v + 1), v + 1).astype(np.int32))
+    return assemble(n, [(KIND_OR, np.zeros(m, np.int32), rows)], name=name or f"hidden2-{k}sat-n{n}"), sigma
+
+
 def maxcut_planted(n: int, seed: int, p_in: float = 0.1, p_out: float = 0.3, w_in: float = 1.0,
                    w_out: float = 2.0) -> Instance:
     """Weighted Max-Cut on a planted two-part graph as weighted 2-XOR: edge
