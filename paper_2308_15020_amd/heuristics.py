@@ -16,7 +16,8 @@ rounded points.  Arms, within a budget of `rounds` iterations:
   w/o heuristics  B restarts, fixed unit weights, every failed round restarts
                   at random ((R)^inf);
   w/ heuristics   B restarts, adaptive weights (ERWA, alpha = 0.4) and
-                  rephasing (ROF)^inf;
+                  rephasing (ROF)^inf; the step size is divided by the mean
+                  weight (--no-step-norm keeps it fixed);
   portfolio       both strategies on one GPU with B/2 restarts each (the same
                   total work as one arm);
   two-device portfolio: both full arms as if on two GPUs (the paper's
@@ -52,13 +53,14 @@ def run(args) -> dict:
             res = {}
             r = solve(prob, B=args.B, rounds=args.rounds, T=args.T, eta=args.eta, weighting=False, policy="R", seed=i)
             res["plain"] = (r.solved, r.rounds, r.seconds)
+            sn = not getattr(args, "no_step_norm", False)
             r = solve(prob, B=args.B, rounds=args.rounds, T=args.T, eta=args.eta, weighting=True, policy="ROF",
-                      seed=i)
+                      seed=i, step_norm=sn)
             res["heuristic"] = (r.solved, r.rounds, r.seconds)
             half = args.B // 2
             probs = [prob, Problem(inst, device=0)]
             r = solve_portfolio(inst, [Arm(half, weighting=False, policy="R", eta=args.eta),
-                                       Arm(args.B - half, weighting=True, policy="ROF", eta=args.eta)],
+                                       Arm(args.B - half, weighting=True, policy="ROF", eta=args.eta, step_norm=sn)],
                                 rounds=args.rounds, T=args.T, seed=i, problems=probs)
             res["portfolio"] = (r.solved, r.rounds, r.seconds)
             probs[1].close()
@@ -89,6 +91,8 @@ def main(argv=None):
     ap.add_argument("--rounds", type=int, default=1000)
     ap.add_argument("--T", type=int, default=50)
     ap.add_argument("--eta", type=float, default=0.1)
+    ap.add_argument("--no-step-norm", action="store_true",
+                    help="weighting arms keep the fixed step size (default: divided by the mean weight)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     table = run(args)
