@@ -89,21 +89,23 @@ __global__ __launch_bounds__(64) void k_fsum2(ReduceArgs<IO> a, int splits)
     }
 }
 
+// parts: 1 = gradient (and step) with level 1 of the sums, 2 = level 2 of
+// the sums, 3 = both in order.
 template <typename IO, bool STEP>
-static hipError_t reduce_impl(const ReduceArgs<IO> &a, hipStream_t s)
+static hipError_t reduce_impl(const ReduceArgs<IO> &a, hipStream_t s, int parts = 3)
 {
     const bool want_g = STEP ? (a.x_step != nullptr) : (a.grad != nullptr);
     const int n_grad = want_g ? a.n : 0;
     const bool rows = a.F != nullptr || a.n_sat != nullptr;
     const int splits = rows ? f_splits(a.rows) : 0;
     const int nbb = (a.B + RED_BLOCK - 1) / RED_BLOCK;
-    if (n_grad + splits > 0) {
+    if ((parts & 1) && n_grad + splits > 0) {
         hipLaunchKernelGGL((k_reduce<IO, STEP>), dim3((unsigned)(n_grad + splits), (unsigned)nbb), dim3(RED_BLOCK),
                            0, s, a, n_grad);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (rows) {
+    if ((parts & 2) && rows) {
         hipLaunchKernelGGL((k_fsum2<IO>), dim3((a.B + 63) / 64), dim3(64), 0, s, a, splits);
         return hipGetLastError();
     }
@@ -119,6 +121,12 @@ hipError_t launch_reduce_f32(const ReduceArgs<float> &r, hipStream_t s)
 hipError_t launch_reduce_f64(const ReduceArgs<double> &r, hipStream_t s)
 {
     return reduce_impl<double, false>(r, s);
+}
+
+hipError_t launch_reduce_part_f32(const ReduceArgs<float> &r, int parts, hipStream_t s)
+{
+    if (r.x_step) return reduce_impl<float, true>(r, s, parts);
+    return reduce_impl<float, false>(r, s, parts);
 }
 
 // ---------------------------------------------------------------- projected step

@@ -1414,6 +1414,9 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
             e = hipStreamCreateWithFlags(&pl->side[q], hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_join[q], hipEventDisableTiming);
         }
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->iter_side, hipStreamNonBlocking);
+        for (hipEvent_t *ev : {&pl->ev_eval, &pl->ev_red, &pl->ev_aux, &pl->ev_sum})
+            if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
         if (e != hipSuccess) st = fail(FFSAT_E_HIP, "side streams: %s", hipGetErrorString(e));
     }
     if (st == FFSAT_OK) st = build_groups(pl);
@@ -1505,6 +1508,9 @@ extern "C" ffsat_status ffsat_plan_destroy(ffsat_plan *pl)
         if (pl->ev_join[q]) (void)hipEventDestroy(pl->ev_join[q]);
     }
     if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+    if (pl->iter_side) (void)hipStreamDestroy(pl->iter_side);
+    for (hipEvent_t ev : {pl->ev_eval, pl->ev_red, pl->ev_aux, pl->ev_sum})
+        if (ev) (void)hipEventDestroy(ev);
     delete pl;
     return FFSAT_OK;
 }
@@ -1746,6 +1752,64 @@ static hipError_t enqueue_iter(ffsat_plan *pl, float *x, float eta, float alpha,
     return hipSuccess;
 }
 
+// The same T iterations with the work that only needs iteration t's counts
+// or level-1 sums moved to a side stream: after evaluation t, the adaptive
+// weights and the reset of U for t+1 run beside the gradient reduction; after
+// reduction t, the level-2 sums (F, n_sat of x_t) run beside evaluation t+1.
+// Evaluation t+1 waits for the weights and the reset; reduction t+1 (which
+// rewrites the level-1 sums) waits for the level-2 sums of t; the caller's
+// stream waits for the side stream at the end.
+static hipError_t enqueue_iters_overlapped(ffsat_plan *pl, float *x, int T, float eta, float alpha, float *F,
+                                           int32_t *n_sat, int32_t *U, hipStream_t s)
+{
+    const ffsat_problem *p = pl->p;
+    hipStream_t q = pl->iter_side;
+    hipError_t e;
+#define ITER_CHK(call) \
+    if ((e = (call)) != hipSuccess) return e
+    ReduceArgs<float> r{};
+    r.n = p->n;
+    r.B = pl->B;
+    r.m = p->m;
+    r.vptr = p->lay[IO_F32].d_vptr;
+    r.vslot = p->lay[IO_F32].d_vslot;
+    r.slot = (const float *)pl->d_slot[IO_F32];
+    r.grad = nullptr;
+    r.x_step = x;
+    r.eta = eta;
+    r.fpart = (const float *)pl->d_fpart[IO_F32];
+    r.cpart = pl->d_cpart;
+    r.rows = pl->fpart_rows[IO_F32];
+    r.ftmp = (float *)pl->d_ftmp[IO_F32];
+    r.ctmp = pl->d_ctmp;
+    r.F = F;
+    r.n_sat = n_sat;
+    if (U) ITER_CHK(launch_fill_i32(U, p->m, 0, s));
+    for (int t = 0; t < T; ++t) {
+        EvalArgs<float> a = base_args<float>(pl, IO_F32, x, nullptr, true);
+        a.do_value = 1;
+        a.want_check = (n_sat || U) ? 1 : 0;
+        a.unsat_bits = nullptr;
+        a.U = U;
+        if (t > 0) ITER_CHK(hipStreamWaitEvent(s, pl->ev_aux, 0));   // weights and reset of t-1
+        ITER_CHK(enqueue_bins<float>(pl, IO_F32, a, s));
+        ITER_CHK(hipEventRecord(pl->ev_eval, s));
+        ITER_CHK(hipStreamWaitEvent(q, pl->ev_eval, 0));
+        if (alpha > 0.f) ITER_CHK(launch_erwa(p->m, U, p->d_w, alpha, pl->d_umax, q));
+        if (U && t < T - 1) ITER_CHK(launch_fill_i32(U, p->m, 0, q));
+        ITER_CHK(hipEventRecord(pl->ev_aux, q));
+        if (t > 0) ITER_CHK(hipStreamWaitEvent(s, pl->ev_sum, 0));   // level-2 sums of t-1 read the level-1 rows
+        ITER_CHK(launch_reduce_part_f32(r, 1, s));
+        ITER_CHK(hipEventRecord(pl->ev_red, s));
+        ITER_CHK(hipStreamWaitEvent(q, pl->ev_red, 0));
+        ITER_CHK(launch_reduce_part_f32(r, 2, q));
+        ITER_CHK(hipEventRecord(pl->ev_sum, q));
+    }
+    ITER_CHK(hipStreamWaitEvent(s, pl->ev_sum, 0));
+#undef ITER_CHK
+    return hipSuccess;
+}
+
 extern "C" ffsat_status ffsat_run_iters(ffsat_plan *pl, float *x, int32_t T, float eta, float alpha, float *F,
                                         int32_t *n_sat, int32_t *U, void *stream)
 {
@@ -1759,6 +1823,7 @@ extern "C" ffsat_status ffsat_run_iters(ffsat_plan *pl, float *x, int32_t T, flo
     if (st != FFSAT_OK) return st;
     if ((st = check_finite<float>(pl, x, s)) != FFSAT_OK) return st;
     auto body = [&](hipStream_t cs) {
+        if (pl->iter_side) return enqueue_iters_overlapped(pl, x, T, eta, alpha, F, n_sat, U, cs);
         hipError_t e = hipSuccess;
         for (int t = 0; t < T && e == hipSuccess; ++t) e = enqueue_iter(pl, x, eta, alpha, F, n_sat, U, cs);
         return e;

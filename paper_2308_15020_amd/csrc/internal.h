@@ -198,6 +198,10 @@ struct ffsat_plan {
     hipStream_t side[N_SIDE] = {};   // bins run concurrently on these (fork/join)
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_join[N_SIDE] = {};
+    // fused iterations: adaptive weights, counter reset and level-2 sums of
+    // iteration t run here beside the gradient reduction and the next evaluation
+    hipStream_t iter_side = nullptr;
+    hipEvent_t ev_eval = nullptr, ev_red = nullptr, ev_aux = nullptr, ev_sum = nullptr;
     bool use_graphs = true;
     bool tuned = false;
     std::string tune_cache;
@@ -240,6 +244,8 @@ struct ReduceArgs {
 };
 hipError_t launch_reduce_f32(const ReduceArgs<float> &r, hipStream_t s);
 hipError_t launch_reduce_f64(const ReduceArgs<double> &r, hipStream_t s);
+// parts: 1 = gradient / step and level 1 of the sums, 2 = level 2, 3 = both
+hipError_t launch_reduce_part_f32(const ReduceArgs<float> &r, int parts, hipStream_t s);
 hipError_t launch_step_f32(int64_t total, int B, float *x, const float *g, const float *eta_b,
                            float eta, hipStream_t s);
 hipError_t launch_step_f64(int64_t total, int B, double *x, const double *g,

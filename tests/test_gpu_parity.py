@@ -325,6 +325,34 @@ def test_run_iters_graph_equals_eager(ffs, mixed):
     prob.set_weights(inst.weights)
 
 
+@pytest.mark.parametrize("use_graphs,side_streams", [(False, True), (True, False), (False, False)])
+def test_run_iters_variants_equal_eval_step_sequence(ffs, mixed, use_graphs, side_streams):
+    """ffsat_run_iters eagerly, and without the side streams (the sequential
+    order), against eval_step + erwa_update calls: bitwise, T = 1 and T = 4
+    (the last iteration's U is kept for the caller, earlier ones are reset)."""
+    inst, prob = mixed
+    B, eta, alpha = 70, 0.05, 0.4
+    x0 = torch.from_numpy(points(inst, B, 62, "uniform")).to(DEV)
+    pr = ffs.Plan(prob, B, use_graphs=use_graphs, side_streams=side_streams)
+    pe = ffs.Plan(prob, B, use_graphs=False)
+    w0 = prob.get_weights().clone()
+    for T in (1, 4):
+        prob.set_weights(w0)
+        xr = x0.clone()
+        o = pr.run_iters(xr, T, eta, alpha)
+        torch.cuda.synchronize()
+        wr = prob.get_weights().clone()
+        prob.set_weights(w0)
+        xe = x0.clone()
+        for _ in range(T):
+            oe = pe.eval_step(xe, eta)
+            pe.erwa_update(oe["U"], alpha)
+        torch.cuda.synchronize()
+        assert torch.equal(xr, xe) and torch.equal(wr, prob.get_weights()), T
+        assert torch.equal(o["F"], oe["F"]) and torch.equal(o["n_sat"], oe["n_sat"]) and torch.equal(o["U"], oe["U"]), T
+    prob.set_weights(inst.weights)
+
+
 def test_autotune_keeps_results(ffs, mixed, tmp_path):
     inst, prob = mixed
     B = 130
