@@ -325,16 +325,21 @@ def test_run_iters_graph_equals_eager(ffs, mixed):
     prob.set_weights(inst.weights)
 
 
-@pytest.mark.parametrize("use_graphs,side_streams", [(False, True), (True, False), (False, False)])
-def test_run_iters_variants_equal_eval_step_sequence(ffs, mixed, use_graphs, side_streams):
-    """ffsat_run_iters eagerly, and without the side streams (the sequential
-    order), against eval_step + erwa_update calls: bitwise, T = 1 and T = 4
-    (the last iteration's U is kept for the caller, earlier ones are reset)."""
+@pytest.mark.parametrize("B", [70, 200, 1024])
+@pytest.mark.parametrize("use_graphs,side_streams,mode", [
+    (False, True, "auto"), (True, True, "auto"), (True, False, "auto"), (False, False, "auto"),
+    (True, True, "per_bin"), (True, True, "group_all"), (False, True, "per_bin")])
+def test_run_iters_variants_equal_eval_step_sequence(ffs, mixed, B, use_graphs, side_streams, mode):
+    """ffsat_run_iters (graph or eager; with the side stream that takes the
+    weights, the reset of U and the level-2 sums, or sequential without side
+    streams; every launch structure) against eval_step + erwa_update calls of
+    a plan with the same launch structure: bitwise, T = 1 and T = 4 (the last
+    iteration's U is kept for the caller, earlier ones are reset)."""
     inst, prob = mixed
-    B, eta, alpha = 70, 0.05, 0.4
+    eta, alpha = 0.05, 0.4
     x0 = torch.from_numpy(points(inst, B, 62, "uniform")).to(DEV)
-    pr = ffs.Plan(prob, B, use_graphs=use_graphs, side_streams=side_streams)
-    pe = ffs.Plan(prob, B, use_graphs=False)
+    pr = ffs.Plan(prob, B, use_graphs=use_graphs, side_streams=side_streams, mode=mode)
+    pe = ffs.Plan(prob, B, use_graphs=False, mode=mode)   # same launch structure: same rounding
     w0 = prob.get_weights().clone()
     for T in (1, 4):
         prob.set_weights(w0)
