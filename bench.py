@@ -43,6 +43,8 @@ WORKLOADS = {
     "large": {"gen": "config3", "seed": 3000, "B": 256,
               "desc": "large hybrid SAT n=100000: 420000 3-SAT, 10000 XOR (len 8-64), 2000 at-least-t "
                       "(len 128-512; FP64 beyond 256), {B} restarts, FP32"},
+    "uf50": {"gen": "config1", "seed": 1000, "B": 1,
+             "desc": "random 3-SAT n=50, m=213 (latency: one restart), {B} restart(s), FP32"},
     "large3sat": {"gen": "config3a", "seed": 3000, "B": 256,
                   "desc": "random 3-SAT n=100000, m=420000 (the 3-SAT part of the large instance), "
                           "{B} restarts, FP32"},
@@ -69,6 +71,9 @@ def parse():
                     help="launch every bin on the caller's stream (no concurrent bins)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON file of tuned tile shapes (read if present, written after tuning)")
+    ap.add_argument("--rq1", action="store_true",
+                    help="instead of the step benchmark: the paper's RQ1 gradient timing (seven formulas, "
+                         "10000 random points, time per point in FP32 and FP64, the FP64 oracle beside it)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -126,6 +131,54 @@ def cpu_baseline(inst, x_np, budget_s=12.0):
                       f"{len(times)} passes, {sum(times):.1f} s in total"}
 
 
+def rq1(args, dev, points=10000, reps=20):
+    """Average time of one objective + gradient evaluation per random point
+    for the paper's seven RQ1 formulas (its Benchmark Details lists their
+    counts and lengths; n = 1000 and t = len/2 are not given there): all
+    points as restarts of one batch, FP32 and FP64 evaluation, HIP events over
+    `reps` evaluations; the FP64 oracle on the host beside it (a subset of the
+    points, all threads and one thread)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads
+    from paper_2308_15020_amd import Plan, Problem
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rows = []
+    for name in workloads.RQ1_SHAPES:
+        inst = workloads.rq1(name)
+        x_np = workloads.points(inst.n_vars, points, workloads.point_seed(6000))
+        prob = Problem(inst, device=0)
+        plan = Plan(prob, points, autotune=not args.no_autotune, tune_cache=args.tune_cache)
+        row = {"formula": name, "n": inst.n_vars, "m": inst.m, "nnz": inst.nnz, "points": points}
+        for dt, key in ((torch.float32, "gpu_f32_us_per_point"), (torch.float64, "gpu_f64_us_per_point")):
+            x = torch.from_numpy(x_np).to(dev, dt)
+            out = plan.eval(x)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                plan.eval(x, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            row[key] = e0.elapsed_time(e1) * 1e3 / reps / points
+        sub = np.ascontiguousarray(x_np[:, :256].astype(np.float64))
+        for nt, key in ((threads, "oracle_us_per_point"), (1, "oracle_1thread_us_per_point")):
+            times = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                oracle.eval_batch(inst, sub, want_g=True, nthreads=nt)
+                times.append(time.perf_counter() - t0)
+            row[key] = float(np.median(times)) * 1e6 / sub.shape[1]
+        row["oracle_threads"] = threads
+        rows.append(row)
+        plan.close()
+        prob.close()
+    print(json.dumps({"metric": "RQ1 gradient computation time per random point", "unit": "us",
+                      "data": "synthetic", "rows": rows}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -140,6 +193,8 @@ def main():
     from paper_2308_15020_amd import Plan, Problem
 
     dev = torch.device("cuda:0")
+    if args.rq1:
+        return rq1(args, dev)
     wl = WORKLOADS[args.workload]
     seed = args.seed if args.workload == "mixed2000" else wl["seed"]
     inst = getattr(workloads, wl["gen"])(seed)
@@ -271,8 +326,16 @@ def main():
         name = "reduce" if k["bin"] == -1 else "grouped eval" if k["bin"] == -2 else (
             f"bin{k['bin']}:{bins[k['bin']]['class']}/{bins[k['bin']]['ct']}/L{bins[k['bin']]['L']}"
             f"/k<={bins[k['bin']]['maxk']}")
-        kernels.append({"kernel": name, "avg_ms": round(k["avg_ms"], 5),
-                        "share": round(k["total_ms"] / sum(q["total_ms"] for q in kern), 4)})
+        ent = {"kernel": name, "avg_ms": round(k["avg_ms"], 5),
+               "share": round(k["total_ms"] / sum(q["total_ms"] for q in kern), 4)}
+        if k["bin"] >= 0:
+            # algorithmic rates of one bin (launched beside others: shares the chip)
+            bd = bins[k["bin"]]
+            sec = k["avg_ms"] / 1e3
+            ent["alg_GBps"] = round(bd["bytes_per_restart"] * B / sec / 1e9, 1)
+            ent["alg_TFLOPps"] = round(bd["flops_per_restart"] * B / sec / 1e12, 2)
+            ent["constraints"] = bd["count"]
+        kernels.append(ent)
 
     res = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
