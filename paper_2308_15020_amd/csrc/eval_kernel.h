@@ -308,6 +308,19 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
     }
 }
 
+// First frequency of wave w of fg that split a constraint's n1 form-1 and
+// nf - n1 form-2 frequencies (and the real chain, on the last wave) into
+// shares of about equal estimated VALU work.  Wave-uniform integer arithmetic.
+__device__ __forceinline__ int freq_bound(int w, int fg, int n1, int nf, int has_real)
+{
+    if (w <= 0) return 0;
+    if (w >= fg) return nf;
+    const int total = 4 * n1 + 5 * (nf - n1) + (has_real ? 4 : 0);
+    const int tgt = (total * w + fg / 2) / fg;
+    const int f = tgt <= 4 * n1 ? (tgt + 3) / 4 : n1 + (tgt - 4 * n1 + 4) / 5;
+    return min(f, nf);
+}
+
 // The work of one wave: unit = (chunk of sp.cpw constraints of the range
 // sp.first .. sp.first + sp.count, restart block rb).  `unit` must be
 // wave-uniform.  Root-of-unity kernels may split a unit's frequencies over
@@ -421,7 +434,11 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
             }
         } else if constexpr (CPLX) {
             const int n1 = ty.n1, nf = ty.n1 + ty.n2;
-            const int f0 = (nf * wg) / fg, f1 = (nf * (wg + 1)) / fg;   // this wave's frequencies
+            // this wave's frequencies: equal shares of the estimated work
+            // (4 units per form-1 frequency, 5 per form-2 one, 4 for the real
+            // chain, which the last wave takes)
+            const int f0 = freq_bound(wg, fg, n1, nf, ty.has_real);
+            const int f1 = freq_bound(wg + 1, fg, n1, nf, ty.has_real);
             FreqT<CT> fr = freqs[ty.tab + f0];
 #pragma unroll 1
             for (int f = f0; f < min(f1, n1); ++f) {
