@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=2000)
     ap.add_argument("--restarts", type=int, default=0, help="restarts (0: the workload's own, 1024 for the default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tts", action="store_true",
+                    help="skip the time-to-solve comparison (learned vs uniform initialisation)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eta", type=float, default=0.05)
     ap.add_argument("--workload", default="mixed2000", choices=sorted(WORKLOADS),
@@ -98,6 +100,28 @@ def measured_traffic(roof):
     if kv.get("source_sha256") != kernel_source_hash() or "traffic_bytes_per_launch" not in kv:
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def time_to_solve():
+    """The second half of the metric: learned initialisation against uniform
+    restarts on planted instances of the mixed n = 2000 shape with 200 XOR
+    constraints (50 training instances, 100 test instances, 256 restarts, 60
+    rounds of 40 steps); the harness's log goes to stderr."""
+    import contextlib
+    from paper_2308_15020_amd import tts
+    argv = ["--train", "50", "--test", "100", "--planted", "--n-xor", "200", "--rounds", "60", "--T", "40",
+            "--eta", "0.3"]
+    t0 = time.perf_counter()
+    with contextlib.redirect_stdout(sys.stderr):
+        s = tts.main(argv)
+    return {"instances": s["instances"], "family": "planted, mixed n=2000 shape, 200 XOR", "B": s["B"],
+            "solve_rate": s["solve_rate"], "both_solved": s["both_solved"],
+            "median_ms": {k: (None if v is None else v * 1e3) for k, v in s["median_s"].items()},
+            "mean_ms": {k: (None if v is None else v * 1e3) for k, v in s["mean_s"].items()},
+            "median_rounds": s["median_rounds"],
+            "learned_vs_polarity_median_ms": [None if v is None else v * 1e3
+                                              for v in s["learned_vs_polarity_median_s"]],
+            "harness_seconds": time.perf_counter() - t0}
 
 
 def cpu_baseline(inst, x_np, budget_s=12.0):
@@ -352,6 +376,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(inst, x_np)
+    if not args.no_tts and args.workload == "mixed2000":
+        res["time_to_solve"] = time_to_solve()
     print(json.dumps(res))
 
 
