@@ -119,6 +119,9 @@ def time_to_solve():
             "median_ms": {k: (None if v is None else v * 1e3) for k, v in s["median_s"].items()},
             "mean_ms": {k: (None if v is None else v * 1e3) for k, v in s["mean_s"].items()},
             "median_rounds": s["median_rounds"],
+            "cactus_at_lower_solve_rate": {
+                (k[:-2] + "_ms" if k.endswith("_s") else k): (v * 1e3 if k.endswith("_s") and v is not None else v)
+                for k, v in s["cactus_at_lower_solve_rate"].items()},
             "learned_vs_polarity_median_ms": [None if v is None else v * 1e3
                                               for v in s["learned_vs_polarity_median_s"]],
             "harness_seconds": time.perf_counter() - t0}

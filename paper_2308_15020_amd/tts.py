@@ -19,8 +19,9 @@ step size, weighting and rephasing policy; the learned arm keeps a quarter of
 its restarts uniform.  A third arm proposes the same way from a non-learned
 polarity lean (each variable towards the sign it occurs in more often), to
 separate what the network learns from the plain occurrence counts.
-Reported: solve rate per arm, and median / mean time over the instances both
-arms solve.
+Reported: solve rate per arm, median / mean time over the instances both
+arms solve, and the time each arm needs to solve as many instances as the
+lower of the two solve rates allows (a point of the cactus curve).
 """
 from __future__ import annotations
 
@@ -129,6 +130,13 @@ def main(argv=None):
     both = [r for r in rows if r["uniform"]["solved"] and r["learned"]["solved"]]
     tu = np.array([r["uniform"]["seconds"] for r in both])
     tl = np.array([r["learned"]["seconds"] for r in both])
+    # cactus measure: the time by which each arm has solved as many instances
+    # as the lower of the two solve rates allows (its k-th fastest solve)
+    k_low = int(min(sum(su), sum(sl)))
+    cactus = {"instances": k_low}
+    for arm in ("uniform", "learned"):
+        ts = sorted(r[arm]["seconds"] for r in rows if r[arm]["solved"])
+        cactus[arm + "_s"] = float(ts[k_low - 1]) if k_low > 0 else None
     summary = {
         "instances": args.test, "planted": args.planted, "n_xor": args.n_xor if args.planted else 500,
         "B": args.B, "rounds": args.rounds, "T": args.T,
@@ -146,6 +154,7 @@ def main(argv=None):
                    "learned": float(np.mean(tl)) if len(both) else None},
         "median_rounds": {"uniform": float(np.median([r["uniform"]["rounds"] for r in both])) if both else None,
                           "learned": float(np.median([r["learned"]["rounds"] for r in both])) if both else None},
+        "cactus_at_lower_solve_rate": cactus,
     }
     log(json.dumps(summary))
     if args.out:

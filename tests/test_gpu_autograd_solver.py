@@ -134,6 +134,8 @@ def test_time_to_solve_harness_runs(ffs):
     assert s["instances"] == 2
     assert 0.0 <= s["solve_rate"]["uniform"] <= 1.0 and 0.0 <= s["solve_rate"]["learned"] <= 1.0
     assert np.isfinite(s["train_loss"]).all()
+    c = s["cactus_at_lower_solve_rate"]
+    assert 0 <= c["instances"] <= 2 and (c["instances"] == 0 or c["learned_s"] > 0)
 
 
 def test_portfolio_arms_keep_their_own_weights(ffs):
