@@ -210,7 +210,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU path (restart "
-                                   "sharding) is described in DESIGN.md and not built",
+                                   "sharding over restarts) is not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
