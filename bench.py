@@ -209,8 +209,8 @@ def rq1(args, dev, points=10000, reps=20):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU path (restart "
-                                   "sharding over restarts) is not built",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU path "
+                                   "(sharding over restarts) is not built",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
