@@ -3,7 +3,8 @@
 * random 3-SAT n=50, m=213, one restart, 200 projected steps: the oracle
   evaluates the GPU's own iterate at every step (FP32 and FP64 paths);
 * mixed n=2000 (8000 OR, 500 XOR, 200 at-least-t), 1024 restarts: sampled
-  restarts against the oracle, in the launch shapes the benchmark uses;
+  restarts against the oracle, in the launch shapes the benchmark uses, and
+  one fused iteration through the benchmark's own graph-replayed path;
 * large mixed n=100000 (420000 3-SAT, 10000 XOR, 2000 at-least-t of length
   128..512), 256 restarts: sampled restarts against the oracle.
 """
@@ -76,6 +77,37 @@ def test_mixed_n2000_b1024_sampled(ffs):
     inst = workloads.config2(workloads.instance_seed(2, 0))
     cols = np.array([0, 1, 63, 64, 511, 777, 1000, 1023])
     print(_sampled(ffs, inst, 1024, cols, ["uniform", "near_corner"], autotune=True))
+
+
+def test_mixed_n2000_b1024_fused_iteration_bench_path(ffs):
+    """The benchmark's own path (autotuned plan, graph-replayed fused
+    iteration with check, projected step and ERWA) at full size: F on sampled
+    restarts, satisfied counts and U over all restarts (bit-exact), the
+    stepped points on sampled restarts and the new weights, against the
+    oracle at the same starting points."""
+    from gpu_cases import var_scale
+    inst = workloads.config2(workloads.instance_seed(2, 0))
+    B, eta, alpha = 1024, 0.05, 0.4
+    prob = ffs.Problem(inst, device=0)
+    plan = ffs.Plan(prob, B, autotune=True)
+    x0 = workloads.points(inst.n_vars, B, workloads.point_seed(workloads.instance_seed(2, 0)))
+    xt = torch.from_numpy(x0).to(DEV)
+    w0 = np.ones(inst.m)
+    prob.set_weights(w0.astype(np.float32))
+    out = to_np(plan.run_iters(xt, 1, eta, alpha))
+    x1 = xt.cpu().numpy()
+    w1 = prob.get_weights().cpu().numpy()
+    cols = np.array([0, 5, 63, 64, 500, 1023])
+    ref = oracle.eval_batch(inst, np.ascontiguousarray(x0[:, cols].astype(np.float64)), want_g=True)
+    wsum = float(inst.m)
+    assert np.max(np.abs(out["F"][cols] - ref["F"])) / wsum <= TOL32
+    chk = oracle.check(inst, x0.astype(np.float64))
+    assert np.array_equal(out["n_sat"], chk["n_sat"]) and np.array_equal(out["U"], chk["U"])
+    want_x1 = np.clip(x0[:, cols].astype(np.float64) - eta * ref["g"], -1.0, 1.0)
+    S = var_scale(inst)[:, None]
+    assert np.max(np.abs(x1[:, cols] - want_x1) / (eta * S)) <= TOL32 + 1e-6
+    want_w1 = oracle.erwa(chk["U"], w0, alpha)
+    assert np.max(np.abs(w1 - want_w1)) <= 1e-6
 
 
 def test_large_mixed_n100000_b256_sampled(ffs):
