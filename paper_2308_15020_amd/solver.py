@@ -11,7 +11,7 @@ from __future__ import annotations
 
 import time
 from dataclasses import dataclass, field
-from typing import Optional
+from typing import Callable, Optional
 
 import numpy as np
 import torch
@@ -46,7 +46,8 @@ class Search:
     def __init__(self, problem: Problem, B: int, T: int = 50, eta: float = 0.05, alpha: float = 0.4,
                  weighting: bool = True, policy: str = "ROF", x0: Optional[torch.Tensor] = None, seed: int = 0,
                  plan: Optional[Plan] = None, optimizer: str = "pgd", max_ls: int = 15,
-                 maximize: Optional[np.ndarray] = None, step_norm: bool = True):
+                 maximize: Optional[np.ndarray] = None, step_norm: bool = True,
+                 random_phase: Optional[Callable[[int], torch.Tensor]] = None):
         if optimizer not in ("pgd", "fista"):
             raise ValueError("optimizer must be 'pgd' or 'fista'")
         if not policy or any(ph not in PHASE_MODE for ph in policy):
@@ -54,6 +55,7 @@ class Search:
         self.problem, self.B, self.T, self.eta, self.alpha = problem, B, T, eta, alpha
         self.weighting, self.policy, self.seed, self.max_ls = weighting, policy, seed, max_ls
         self.step_norm = step_norm
+        self.random_phase = random_phase
         self.eta_eff = eta
         dev = problem.device
         self.plan = plan or Plan(problem, B)
@@ -103,7 +105,10 @@ class Search:
                 wm = float(self.problem.get_weights().mean().item())
                 self.eta_eff = self.eta / max(wm, 1e-6)
         phase = self.policy[r % len(self.policy)]
-        self.plan.rephase(self.x, PHASE_MODE[phase], seed=self.seed * 1000003 + r + 1)
+        if phase == "R" and self.random_phase is not None:
+            self.x.copy_(self.random_phase(r))
+        else:
+            self.plan.rephase(self.x, PHASE_MODE[phase], seed=self.seed * 1000003 + r + 1)
         if self.state is not None:
             self.state = self.plan.fista_state(self.x, self.eta)
 
@@ -112,7 +117,8 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
           alpha: float = 0.4, weighting: bool = True, policy: str = "ROF",
           x0: Optional[torch.Tensor] = None, seed: int = 0, time_limit: Optional[float] = None,
           plan: Optional[Plan] = None, log: bool = False, optimizer: str = "pgd",
-          max_ls: int = 15, maximize: Optional[np.ndarray] = None, step_norm: bool = True) -> SolveResult:
+          max_ls: int = 15, maximize: Optional[np.ndarray] = None, step_norm: bool = True,
+          random_phase: Optional[Callable[[int], torch.Tensor]] = None) -> SolveResult:
     """Alg. 1: returns at the first round in which some restart's rounded point
     satisfies every constraint (decided by the exact checker).
 
@@ -129,6 +135,8 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
     constraints its rounded point satisfies; the run keeps the best scoring
     assignment over all rounds and stops early only if every constraint holds.
     The search itself still uses the problem's (adaptive) weights.
+    random_phase: draws the points of the random phase after failed round r
+    (default: U[-1, 1] from the library), e.g. a fresh learned proposal.
     step_norm: with adaptive weights, divide the projected step size by the
     mean weight after every update (the weights shrink towards U/max U, which
     would otherwise shorten a fixed step; the paper's line search adapts the
@@ -138,7 +146,8 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
     t_start = time.perf_counter()
     m = problem.m
     S = Search(problem, B, T=T, eta=eta, alpha=alpha, weighting=weighting, policy=policy, x0=x0, seed=seed,
-               plan=plan, optimizer=optimizer, max_ls=max_ls, maximize=maximize, step_norm=step_norm)
+               plan=plan, optimizer=optimizer, max_ls=max_ls, maximize=maximize, step_norm=step_norm,
+               random_phase=random_phase)
     best = -1
     for r in range(rounds):
         b, cur = S.run_round()

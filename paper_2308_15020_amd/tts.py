@@ -11,6 +11,8 @@ hard an instance is for the continuous search).  Training instances use seeds 10
 20000.. (disjoint).  The network is trained on the mean signs of the best end
 points of uniform-init searches (1024 restarts per training instance).
 
+The learned and polarity arms also draw every random phase after a failed
+round from their own lean (a fresh proposal), unless --no-reuse-proposal.
 Per test instance and arm, the clock runs from the start of initialisation
 (network inference and proposal included for the learned arm) to the round in
 which a restart's rounded point passes the exact checker, within a budget of
@@ -61,11 +63,16 @@ def run_arm(prob: Problem, plan: Plan, net, args, seed: int, mu_fixed=None) -> d
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     x0 = None
+    again = None
     if net is not None:
         mu = net.forward(prob) if mu_fixed is None else mu_fixed
         x0 = net.propose(plan, mu, frac_learned=args.frac, sigma=args.sigma, seed=seed)
+        if args.reuse_proposal:
+            # the random phase draws a fresh proposal from the same lean
+            def again(r):
+                return net.propose(plan, mu, frac_learned=args.frac, sigma=args.sigma, seed=seed * 1009 + r + 1)
     res = solve(prob, B=args.B, rounds=args.rounds, T=args.T, eta=args.eta, policy=args.policy, x0=x0,
-                seed=seed, plan=plan)
+                seed=seed, plan=plan, random_phase=again)
     torch.cuda.synchronize()
     return {"solved": bool(res.solved), "seconds": time.perf_counter() - t0, "rounds": res.rounds,
             "best_sat": res.best_sat}
@@ -86,6 +93,9 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--planted", action="store_true")
     ap.add_argument("--n-xor", type=int, default=500, help="XOR constraints of a planted instance")
+    ap.add_argument("--no-reuse-proposal", dest="reuse_proposal", action="store_false",
+                    help="learned and polarity arms: the random phase after a failed round draws U[-1, 1] "
+                         "(default: a fresh proposal from the same lean)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
 
@@ -139,6 +149,7 @@ def main(argv=None):
         cactus[arm + "_s"] = float(ts[k_low - 1]) if k_low > 0 else None
     summary = {
         "instances": args.test, "planted": args.planted, "n_xor": args.n_xor if args.planted else 500,
+        "reuse_proposal": bool(args.reuse_proposal),
         "B": args.B, "rounds": args.rounds, "T": args.T,
         "eta": args.eta, "policy": args.policy, "frac_learned": args.frac, "sigma": args.sigma,
         "train_instances": args.train, "train_loss": [hist[0], hist[-1]],
