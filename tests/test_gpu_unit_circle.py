@@ -137,3 +137,20 @@ def test_precision_loss_near_corners(ffs):
     want = oracle.check(inst, x.astype(np.float32).astype(np.float64))
     assert np.array_equal(chk["n_sat"].cpu().numpy(), want["n_sat"])
     assert np.array_equal(chk["unsat_bits"].cpu().numpy().view(np.uint32), want["unsat_bits"])
+
+
+def test_ablation_harness_runs(ffs, monkeypatch):
+    """The basis ablation end to end on two short lengths: every cell present,
+    the bounded basis in FP64 agrees with itself, the unit circle in FP64 is
+    accurate at these lengths."""
+    import argparse
+    from paper_2308_15020_amd import ablation
+    monkeypatch.setattr(ablation, "KS", (8, 16))
+    rows = ablation.run(argparse.Namespace(B=64, per_k=3, reps=2))
+    assert len(rows) == 2 * 2 * 2 * 2
+    for r in rows:
+        assert r["max_err"] is not None and r["nonfinite"] == 0.0 and r["ms_per_eval"] > 0
+        if r["basis"] == "pb" and r["dtype"] == "float64":
+            assert r["max_err"] == 0.0
+        if r["basis"] == "uc" and r["dtype"] == "float64":
+            assert r["max_err"] <= 1e-10
