@@ -189,6 +189,8 @@ def solve_portfolio(inst, arms, rounds: int = 100, T: int = 50, seed: int = 0, d
     probs = problems if problems is not None else [Problem(inst, device=device) for _ in arms]
     if len(probs) != len(arms):
         raise ValueError("one problem per arm")
+    if len({id(p) for p in probs}) != len(probs):
+        raise ValueError("each arm needs its own problem object (the adaptive weights live on it)")
     m = probs[0].m
     searches = [Search(p, a.B, T=T, eta=a.eta, alpha=a.alpha, weighting=a.weighting, policy=a.policy,
                        seed=seed * 7919 + i, optimizer=a.optimizer, step_norm=a.step_norm)

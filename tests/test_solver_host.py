@@ -19,3 +19,10 @@ def test_portfolio_needs_one_problem_per_arm():
     from paper_2308_15020_amd.solver import Arm, solve_portfolio
     with pytest.raises(ValueError):
         solve_portfolio(None, [Arm(8), Arm(8)], problems=[object()])
+
+
+def test_portfolio_rejects_a_shared_problem():
+    from paper_2308_15020_amd.solver import Arm, solve_portfolio
+    shared = object()
+    with pytest.raises(ValueError):
+        solve_portfolio(None, [Arm(8), Arm(8)], problems=[shared, shared])
