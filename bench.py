@@ -1,26 +1,43 @@
 """Benchmark: literal-gradient evaluations per second on one MI355X.
 
-Workload: the mixed hybrid instance n = 2000 (8000 OR clauses of length
-3..7, 500 XOR of length 3..20, 200 at-least-t of length 10..100), 1024
-restarts, FP32, seeded synthetic data.  One step is one pass of the whole
-per-batch hot path: objective and gradient of every constraint at every
-restart (with the deterministic reduction into the gradient), the projected
-step, the exact round-and-check, and the adaptive-weight update.
+Headline workload: the large hybrid instance (n = 100000 variables; 420000
+random 3-SAT clauses, 10000 XOR constraints of length 8..64, 2000
+at-least-t constraints of length 128..512), 256 restarts, FP32 with FP64
+root-of-unity products for constraints longer than 256 literals, seeded
+synthetic data.  One step is one pass of the whole per-batch hot path:
+objective and gradient of every constraint at every restart, the
+deterministic reduction into the gradient, the projected step, the exact
+round-and-check and the adaptive-weight update, replayed from a captured
+graph.
 
 value = nnz * B / (seconds per step): one "literal-gradient evaluation" is
 one (literal occurrence, restart) pair whose gradient contribution and the
 objective are produced.
 
-The JSON line carries `roofline` for the kernel that takes the most time
-(timed live with HIP events on the stream it runs on) and `cpu_baseline`,
-the FP64 oracle timed on the host cores on a bounded sample of the same
-workload.
+`roofline` describes the kernel with the most time per step, timed live
+with HIP events on the stream it runs on.  One convention throughout:
+root-of-unity kernels do 10 k^2 FMA-class operations per (constraint,
+restart) (2 FLOP each) against the published vector peak of their
+arithmetic type (FP32 157.3, FP64 78.6 TFLOP/s); transform-free chains and
+the reduction move 8 B per (literal, restart) in the evaluation (a gathered
+point, a slot written) plus 4 B per (literal, restart) and 8 B per
+(variable, restart) in the reduction, against 8 TB/s; a kernel is bound by
+whichever of the two its work needs longer on.  Hardware counters of the
+same kernel (VALU instructions, HBM bytes) come from the committed rocprofv3
+summary in profiles/ while the kernel sources are unchanged.
+
+Secondary workloads measured in the same run: the mixed n = 2000 instance
+(1024 restarts) and the 3-SAT part of the large instance alone.  The time
+to solve with learned against uniform initialisation (the metric's second
+half) follows.  `cpu_baseline`: the FP64 oracle on the host cores, on a
+leading subset of the headline's restarts.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -30,43 +47,43 @@ sys.path.insert(0, ROOT)
 METRIC = "literal-gradient evals/s at 1 GPU (vs FP64 oracle); time-to-solve learned vs random"
 UNIT = "literal-gradient evals/s"
 HBM_PEAK_GBS = 8000.0
-# FP32 vector FMA without packed math (disabled for all device code here) and
-# FP64 vector FMA: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz.
-VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-VALU_PEAK_PACKED_TFLOPS = 157.3
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}     # published vector peaks
+CLOCK_GHZ, SIMDS = 2.4, 1024                  # 256 CUs x 4 SIMDs
+OPS_PER_K2 = 10.0                              # root-of-unity work per (constraint, restart)
 
 
 WORKLOADS = {
-    "mixed2000": {"gen": "config2", "seed": 2000, "B": 1024,
+    "large": {"gen": "config3", "seed": 3000, "B": 256, "steps": 30, "warmup": 3,
+              "desc": "large hybrid SAT n=100000: 420000 3-SAT, 10000 XOR (len 8-64), 2000 at-least-t "
+                      "(len 128-512, t ~ U{1..len/2}; FP64 root-of-unity products beyond 256 literals), "
+                      "{B} restarts, FP32"},
+    "mixed2000": {"gen": "config2", "seed": 2000, "B": 1024, "steps": 200, "warmup": 20,
                   "desc": "mixed hybrid SAT n=2000: 8000 OR (len 3-7), 500 XOR (len 3-20), "
                           "200 at-least-t (len 10-100), {B} restarts, FP32"},
-    "large": {"gen": "config3", "seed": 3000, "B": 256,
-              "desc": "large hybrid SAT n=100000: 420000 3-SAT, 10000 XOR (len 8-64), 2000 at-least-t "
-                      "(len 128-512; FP64 beyond 256), {B} restarts, FP32"},
-    "uf50": {"gen": "config1", "seed": 1000, "B": 1,
-             "desc": "random 3-SAT n=50, m=213 (latency: one restart), {B} restart(s), FP32"},
-    "large3sat": {"gen": "config3a", "seed": 3000, "B": 256,
+    "large3sat": {"gen": "config3a", "seed": 3000, "B": 256, "steps": 100, "warmup": 10,
                   "desc": "random 3-SAT n=100000, m=420000 (the 3-SAT part of the large instance), "
                           "{B} restarts, FP32"},
+    "uf50": {"gen": "config1", "seed": 1000, "B": 1, "steps": 200, "warmup": 20,
+             "desc": "random 3-SAT n=50, m=213 (latency: one restart), {B} restart(s), FP32"},
 }
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--seed", type=int, default=2000)
-    ap.add_argument("--restarts", type=int, default=0, help="restarts (0: the workload's own, 1024 for the default)")
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (0: the workload's default)")
+    ap.add_argument("--warmup", type=int, default=-1, help="untimed warm-up steps (-1: the workload's default)")
+    ap.add_argument("--restarts", type=int, default=0, help="restarts (0: the workload's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tts", action="store_true",
                     help="skip the time-to-solve comparison (learned vs uniform initialisation)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="measure the headline workload only")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eta", type=float, default=0.05)
-    ap.add_argument("--workload", default="mixed2000", choices=sorted(WORKLOADS),
-                    help="instance family (the default is the headline configuration)")
-    ap.add_argument("--chunk", type=int, default=20,
-                    help="iterations per graph replay in the headline loop")
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS),
+                    help="headline instance family (default: the large instance)")
+    ap.add_argument("--chunk", type=int, default=10, help="iterations per graph replay in the timed loop")
     ap.add_argument("--mode", default="auto", choices=["auto", "per_bin", "group_all", "group_dft"],
                     help="launch structure of the evaluation (auto: chosen by the autotuner)")
     ap.add_argument("--serial", action="store_true",
@@ -78,59 +95,220 @@ def parse():
                          "10000 random points, time per point in FP32 and FP64, the FP64 oracle beside it)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     return ap.parse_args()
 
 
-def measured_traffic(roof):
-    """HBM bytes per launch of the grouped evaluation kernel from the committed
-    rocprofv3 counter summary, if the kernel sources are unchanged since the
-    counters were taken (else None)."""
-    if not roof.get("kernel", "").startswith("grouped evaluation launch"):
-        return None
+# ----------------------------------------------------------------------------- roofline
+
+def bin_work(bd, B):
+    """Algorithmic work of one evaluation bin per launch: (flop, bytes, dtype)."""
+    flop = 2.0 * OPS_PER_K2 * bd.get("k2_per_restart", 0.0) * B
+    nbytes = 8.0 * bd["lits"] * B
+    return flop, nbytes, bd["ct"]
+
+
+def bound_of(flop, nbytes, dt):
+    t_alu = flop / (PEAK_TFLOPS[dt] * 1e12)
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    return "alu" if t_alu >= t_hbm else "hbm"
+
+
+def roofline_entry(label, flop, nbytes, dt, avg_s, launches_per_step):
+    bound = bound_of(flop, nbytes, dt)
+    ent = {"kernel": label, "avg_launch_ms": avg_s * 1e3, "launches_per_step": launches_per_step,
+           "flop_per_launch": flop, "bytes_per_launch": nbytes, "arith": dt}
+    if bound == "alu":
+        ach = flop / avg_s / 1e12
+        ent.update({"bound": "alu", "achieved": ach, "peak": PEAK_TFLOPS[dt],
+                    "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[dt]})
+    else:
+        ach = nbytes / avg_s / 1e9
+        ent.update({"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS})
+    return ent
+
+
+def kernel_card(workload):
+    """Counters of the workload's dominant kernel from the committed rocprofv3
+    summary (profiles/<workload>_counters.txt), if the kernel sources hash to
+    the value recorded with them; else None."""
     from paper_2308_15020_amd.profsum import kernel_source_hash
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                        "eval_group_mixed2000_counters.txt")
+    path = os.path.join(ROOT, "profiles", f"{workload}_counters.txt")
     if not os.path.exists(path):
         return None
     kv = {}
     for line in open(path):
-        if ":" in line:
+        if ":" in line and not line.startswith(" "):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != kernel_source_hash() or "traffic_bytes_per_launch" not in kv:
+    if kv.get("source_sha256") != kernel_source_hash():
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return kv
 
 
-def time_to_solve():
-    """The second half of the metric: learned initialisation against uniform
-    restarts on planted instances of the mixed n = 2000 shape with 200 XOR
-    constraints (50 training instances, 100 test instances, 256 restarts, 60
-    rounds of 40 steps); the harness's log goes to stderr."""
-    import contextlib
-    from paper_2308_15020_amd import tts
-    argv = ["--train", "50", "--test", "100", "--planted", "--n-xor", "200", "--rounds", "60", "--T", "40",
-            "--eta", "0.3"]
-    t0 = time.perf_counter()
-    with contextlib.redirect_stdout(sys.stderr):
-        s = tts.main(argv)
-    return {"instances": s["instances"], "family": "planted, mixed n=2000 shape, 200 XOR", "B": s["B"],
-            "solve_rate": s["solve_rate"], "both_solved": s["both_solved"],
-            "median_ms": {k: (None if v is None else v * 1e3) for k, v in s["median_s"].items()},
-            "mean_ms": {k: (None if v is None else v * 1e3) for k, v in s["mean_s"].items()},
-            "median_rounds": s["median_rounds"],
-            "cactus_at_lower_solve_rate": {
-                (k[:-2] + "_ms" if k.endswith("_s") else k): (v * 1e3 if k.endswith("_s") and v is not None else v)
-                for k, v in s["cactus_at_lower_solve_rate"].items()},
-            "learned_vs_polarity_median_ms": [None if v is None else v * 1e3
-                                              for v in s["learned_vs_polarity_median_s"]],
-            "harness_seconds": time.perf_counter() - t0}
+def measure(name, args, dev, headline):
+    """Runs one workload: an eager loop with library events (per-kernel
+    launch times), then the timed loop of graph-replayed fused iterations."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2308_15020_amd import Plan, Problem
+    wl = WORKLOADS[name]
+    steps = args.steps if (headline and args.steps > 0) else wl["steps"]
+    warmup = args.warmup if (headline and args.warmup >= 0) else wl["warmup"]
+    inst = getattr(workloads, wl["gen"])(wl["seed"])
+    B = args.restarts if (headline and args.restarts) else wl["B"]
+    x_np = workloads.points(inst.n_vars, B, workloads.point_seed(wl["seed"]))
+    t_setup = time.perf_counter()
+    prob = Problem(inst, device=0)
+    plan = Plan(prob, B, autotune=not args.no_autotune, tune_cache=args.tune_cache, side_streams=not args.serial,
+                mode=args.mode)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    x0 = torch.from_numpy(x_np).to(dev)
+    x = x0.clone()
+    outs = {"F": torch.empty(B, device=dev), "n_sat": torch.empty(B, dtype=torch.int32, device=dev),
+            "U": torch.empty(inst.m, dtype=torch.int32, device=dev)}
+
+    # eager loop: objective, gradient, exact check of x_t and the projected
+    # step in one pass, then the adaptive weights; library events per kernel
+    def eager_step():
+        o = plan.eval_step(x, args.eta)
+        plan.erwa_update(o["U"], 0.4)
+
+    prof_steps = max(1, min(steps, 10))
+    for _ in range(max(1, warmup // 2)):
+        eager_step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_read(reset=True)
+    for _ in range(prof_steps):
+        eager_step()
+    torch.cuda.synchronize()
+    prof = plan.profile_read(reset=True)
+    plan.profile(False)
+
+    # timed loop: chunk fused iterations per graph replay
+    chunk = max(1, min(args.chunk, steps))
+    while steps % chunk:
+        chunk -= 1
+    x.copy_(x0)
+    prob.set_weights(inst.weights_or_ones())
+    for _ in range(max(1, warmup // chunk)):
+        plan.run_iters(x, chunk, args.eta, 0.4, out=outs)     # capture and warm-up, outside the timed region
+    x.copy_(x0)
+    prob.set_weights(inst.weights_or_ones())
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps // chunk):
+        plan.run_iters(x, chunk, args.eta, 0.4, out=outs)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ms_per_step = (t3 - t2) * 1e3 / steps
+    value = inst.nnz * B / (ms_per_step / 1e3)
+    n_sat_last = int(outs["n_sat"].max().item())
+
+    desc = plan.describe()
+    bins = desc["bins"]["f32"]
+    kern = [k for k in prof["kernels"] if k["io"] == "f32"]
+    entries = []
+    for k in kern:
+        avg_s = k["avg_ms"] / 1e3
+        per_step = k["launches"] / prof_steps
+        if k["bin"] == -2:
+            grp = [b for b in bins if b["in_group"]]
+            flop = sum(bin_work(b, B)[0] for b in grp)
+            nbytes = sum(bin_work(b, B)[1] for b in grp)
+            label = (f"grouped FP32 evaluation launch ({len(grp)} bins, "
+                     f"{sum(1 for b in grp if b['class'] == 'dft')} root-of-unity, "
+                     f"{sum(b['count'] for b in grp)} constraints)")
+            ent = roofline_entry(label, flop, nbytes, "f32", avg_s, per_step)
+            ent["kernel_name"] = "k_eval_group"
+        elif k["bin"] >= 0:
+            bd = bins[k["bin"]]
+            flop, nbytes, dt = bin_work(bd, B)
+            label = (f"eval bin {k['bin']} ({bd['class']}, {bd['ct']} arithmetic, seg {bd['seg']}, L {bd['L']}, "
+                     f"{bd['count']} constraints, len <= {bd['maxk']})")
+            ent = roofline_entry(label, flop, nbytes, dt, avg_s, per_step)
+            ent["kernel_name"] = (f"k_eval<float, {'double' if bd['ct'] == 'f64' else 'float'}, {bd['seg']}, "
+                                  f"{bd['L']}, {'true' if bd['class'] == 'dft' else 'false'}>")
+        else:
+            nbytes = (4.0 * inst.nnz + 8.0 * inst.n_vars) * B
+            ent = roofline_entry("gradient reduction + projected step", 0.0, nbytes, "f32", avg_s, per_step)
+            ent["kernel_name"] = "k_reduce<float, true>"
+        ent["ms_per_step"] = avg_s * 1e3 * per_step
+        entries.append(ent)
+    # kernels of one template are reported together (split bins of one shape)
+    merged = {}
+    for e in entries:
+        m = merged.get(e["kernel_name"])
+        if m is None:
+            merged[e["kernel_name"]] = dict(e, _t=e["avg_launch_ms"] * e["launches_per_step"], _f=e["flop_per_launch"]
+                                            * e["launches_per_step"], _b=e["bytes_per_launch"] * e["launches_per_step"],
+                                            _n=e["launches_per_step"], parts=1)
+        else:
+            m["_t"] += e["avg_launch_ms"] * e["launches_per_step"]
+            m["_f"] += e["flop_per_launch"] * e["launches_per_step"]
+            m["_b"] += e["bytes_per_launch"] * e["launches_per_step"]
+            m["_n"] += e["launches_per_step"]
+            m["parts"] += 1
+    kernels = []
+    for kname, m in merged.items():
+        n = m["_n"]
+        ent = roofline_entry(m["kernel"] if m["parts"] == 1 else f"{kname} ({m['parts']} bin ranges)",
+                             m["_f"] / n, m["_b"] / n, m["arith"], m["_t"] / n / 1e3, n)
+        ent["kernel_name"] = kname
+        ent["ms_per_step"] = m["_t"]
+        kernels.append(ent)
+    kernels.sort(key=lambda e: -e["ms_per_step"])
+    dom = dict(kernels[0])
+    dom["traffic"] = None
+    card = kernel_card(name)
+    if card is not None and card.get("kernel_name") == dom["kernel_name"]:
+        if "traffic_bytes_per_launch" in card:
+            dom["traffic"] = float(card["traffic_bytes_per_launch"])
+            dom["traffic_to_algorithmic_bytes"] = dom["traffic"] / max(dom["bytes_per_launch"], 1.0)
+        if "valu_insts_per_launch" in card:
+            vi = float(card["valu_insts_per_launch"])
+            # wave64 VALU instructions issue one per 4 cycles per SIMD
+            dom["valu_issue"] = vi * 4.0 / (SIMDS * CLOCK_GHZ * 1e9 * dom["avg_launch_ms"] / 1e3)
+            dom["valu_insts_per_launch"] = vi
+        if "rocprof_avg_us" in card:
+            dom["rocprof_avg_launch_ms"] = float(card["rocprof_avg_us"]) / 1e3
+    for e in kernels:
+        for key in ("flop_per_launch", "bytes_per_launch", "achieved", "frac", "avg_launch_ms", "ms_per_step"):
+            if key in e and isinstance(e[key], float):
+                e[key] = float(f"{e[key]:.5g}")
+    res = {"workload": wl["desc"].format(B=B), "n_vars": inst.n_vars, "n_cons": inst.m, "nnz": inst.nnz,
+           "restarts": B, "steps": steps, "warmup": warmup, "ms_per_step": ms_per_step, "value": value,
+           "iterations_per_graph_replay": chunk, "setup_s_incl_autotune": setup_s,
+           "best_n_sat_last_step": n_sat_last, "roofline": dom, "kernels": kernels[:12]}
+    out = (res, inst, x_np)
+    plan.close()
+    prob.close()
+    return out
 
 
-def cpu_baseline(inst, x_np, budget_s=12.0):
-    """FP64 oracle on the host: the same instance and points (all restarts
-    when one pass takes under a third of the budget, else a leading subset),
-    passes repeated until about `budget_s` of work; median pass time."""
+# ----------------------------------------------------------------------------- host baseline
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(inst, x_np, budget_s=15.0):
+    """FP64 oracle on the host: the same instance and points.  A probe on as
+    many restarts as threads sizes a leading subset that takes about a third
+    of the budget per pass; passes repeat until the budget is spent; the
+    median pass gives evals/s (the oracle's cost is linear in the restarts,
+    which are independent)."""
     import numpy as np
 
     import oracle
@@ -139,24 +317,56 @@ def cpu_baseline(inst, x_np, budget_s=12.0):
     Bp = max(1, min(B, threads))
     probe = np.ascontiguousarray(x_np[:, :Bp].astype(np.float64))
     t0 = time.perf_counter()
-    oracle.eval_batch(inst, probe, want_g=True, nthreads=threads)
+    r = oracle.eval_batch(inst, probe, want_g=True, nthreads=threads)
     t_probe = max(time.perf_counter() - t0, 1e-6)
+    used = r["threads"]
     Bs = min(B, Bp * max(1, int(budget_s / 3.0 / t_probe)))
+    times = [t_probe] if Bs == Bp else []
     sub = np.ascontiguousarray(x_np[:, :Bs].astype(np.float64))
-    times = []
-    used = 1
     t_start = time.perf_counter()
-    while len(times) < 3 or (time.perf_counter() - t_start < budget_s and len(times) < 1000):
+    while len(times) < 3 and (time.perf_counter() - t_start < budget_s or not times):
         t0 = time.perf_counter()
         r = oracle.eval_batch(inst, sub, want_g=True, nthreads=threads)
         times.append(time.perf_counter() - t0)
         used = r["threads"]
     t = float(np.median(times))
     return {"value": inst.nnz * Bs / t, "unit": UNIT, "cores": int(used), "kind": "oracle",
-            "sample": f"{Bs} of {B} restarts of the same instance and points, F and gradient in FP64 "
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "sample": f"the first {Bs} of {B} restarts of the same instance and points (restarts are "
+                      f"independent, so evals/s = nnz * {Bs} / pass time), F and gradient in FP64 "
                       f"(count-lattice recursion for at-least-t, closed forms for OR/XOR); median of "
-                      f"{len(times)} passes, {sum(times):.1f} s in total"}
+                      f"{len(times)} passes of {t:.2f} s, {int(used)} OpenMP threads"}
 
+
+# ----------------------------------------------------------------------------- time to solve
+
+def time_to_solve():
+    """The second half of the metric: learned initialisation against uniform
+    restarts (test instances disjoint from the training ones); the harness's
+    log goes to stderr."""
+    import contextlib
+    from paper_2308_15020_amd import tts
+    argv = ["--train", "50", "--test", "100", "--planted", "--n-xor", "200", "--rounds", "60", "--T", "40",
+            "--eta", "0.3"]
+    t0 = time.perf_counter()
+    with contextlib.redirect_stdout(sys.stderr):
+        s = tts.main(argv)
+    ms = lambda v: None if v is None else v * 1e3  # noqa: E731
+    return {"instances": s["instances"], "family": s["family"], "B": s["B"], "rounds": s["rounds"], "T": s["T"],
+            "reuse_proposal": s["reuse_proposal"],
+            "solve_rate": s["solve_rate"], "both_solved": s["both_solved"],
+            "median_ms": {k: ms(v) for k, v in s["median_s"].items()},
+            "mean_ms": {k: ms(v) for k, v in s["mean_s"].items()},
+            "median_rounds": s["median_rounds"],
+            "cactus_at_lower_solve_rate": {
+                (k[:-2] + "_ms" if k.endswith("_s") else k): (ms(v) if k.endswith("_s") else v)
+                for k, v in s["cactus_at_lower_solve_rate"].items()},
+            "learned_vs_polarity_median_ms": [ms(v) for v in s["learned_vs_polarity_median_s"]],
+            "learned_first_round_only_median_ms": ms(s.get("learned_once_median_s")),
+            "harness_seconds": time.perf_counter() - t0}
+
+
+# ----------------------------------------------------------------------------- RQ1
 
 def rq1(args, dev, points=10000, reps=20):
     """Average time of one objective + gradient evaluation per random point
@@ -210,46 +420,13 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU path "
-                                   "(sharding over restarts) is not built",
-                          "n_gpus": args.gpus}))
+                                   "(sharding over restarts) is not built", "n_gpus": args.gpus}))
         sys.exit(2)
-    import numpy as np
     import torch
-
-    import workloads
-    from paper_2308_15020_amd import Plan, Problem
 
     dev = torch.device("cuda:0")
     if args.rq1:
         return rq1(args, dev)
-    wl = WORKLOADS[args.workload]
-    seed = args.seed if args.workload == "mixed2000" else wl["seed"]
-    inst = getattr(workloads, wl["gen"])(seed)
-    B = args.restarts if args.restarts else wl["B"]
-    x_np = workloads.points(inst.n_vars, B, workloads.point_seed(seed))
-    prob = Problem(inst, device=0)
-    plan = Plan(prob, B, autotune=not args.no_autotune, tune_cache=args.tune_cache, side_streams=not args.serial,
-                mode=args.mode)
-    x0 = torch.from_numpy(x_np).to(dev)
-    x = x0.clone()
-    out = {"F": torch.empty(B, device=dev), "grad": torch.empty(inst.n_vars, B, device=dev)}
-    U = torch.empty(inst.m, dtype=torch.int32, device=dev)
-    n_sat = torch.empty(B, dtype=torch.int32, device=dev)
-
-    import ctypes as C
-    from paper_2308_15020_amd._lib import check, lib
-    L = lib()
-    stream = C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
-    ph = plan.handle
-    p = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
-    eta = C.c_float(args.eta)
-
-    def step():
-        # objective, gradient, exact check of x_t and the projected step to
-        # x_{t+1} in one pass, then the adaptive weights from the check
-        check(L.ffsat_eval_step(ph, p(x), eta, p(out["F"]), p(n_sat), p(U), stream))
-        check(L.ffsat_erwa_update(ph, p(U), C.c_float(0.4), stream))
-
     if args.copy_mib > 0:
         # a plain elementwise kernel of known size: reads and writes copy_mib MiB
         src = torch.ones(args.copy_mib * 262144, dtype=torch.float32, device=dev)
@@ -259,128 +436,41 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    x.copy_(x0)
-    prob.set_weights(inst.weights_or_ones())
-    torch.cuda.synchronize()
-    plan.profile(True)
-    plan.profile_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = plan.profile_read(reset=True)
-    plan.profile(False)
-    # the same iterations without timing events, for the headline number:
-    # replayed from a captured graph (ffsat_run_iters), chunk steps at a time
-    x.copy_(x0)
-    prob.set_weights(inst.weights_or_ones())
-    chunk = max(1, min(args.chunk, args.steps))
-    while args.steps % chunk:                                # one graph for the whole loop
-        chunk -= 1
-    outs = {"F": out["F"], "n_sat": n_sat, "U": U}
-    plan.run_iters(x, chunk, args.eta, 0.4, out=outs)          # capture outside the timed region
-    x.copy_(x0)
-    prob.set_weights(inst.weights_or_ones())
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    done = 0
-    while done < args.steps:
-        c = min(chunk, args.steps - done)
-        plan.run_iters(x, c, args.eta, 0.4, out=outs)
-        done += c
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    ms_per_step = (t3 - t2) * 1e3 / args.steps
-    value = inst.nnz * B / (ms_per_step / 1e3)
-
-    desc = plan.describe()
-    bins = desc["bins"]["f32"]
-    kern = [k for k in prof["kernels"] if k["io"] == "f32"]
-    dom = max(kern, key=lambda k: k["total_ms"])
-    avg_s = dom["avg_ms"] / 1e3
-    if dom["bin"] == -2:
-        # the grouped launch: every bin in the group; bound by whichever
-        # peak its algorithmic work needs longer on
-        grp = [b for b in bins if b["in_group"]]
-        flops = sum(b["flops_per_restart"] for b in grp) * B
-        nbytes = sum(b["bytes_per_restart"] for b in grp) * B
-        alu_bound = flops / (VALU_PEAK_TFLOPS * 1e12) >= nbytes / (HBM_PEAK_GBS * 1e9)
-        n_dft = sum(1 for b in grp if b["class"] == "dft")
-        label = (f"grouped evaluation launch ({len(grp)} bins, {n_dft} root-of-unity, "
-                 f"{sum(b['count'] for b in grp)} constraints)")
-        if alu_bound:
-            achieved = flops / avg_s / 1e12
-            roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / VALU_PEAK_TFLOPS, "traffic": None, "kernel": label,
-                    "avg_launch_ms": dom["avg_ms"], "flops_per_launch": flops, "bytes_per_launch": nbytes,
-                    "frac_of_packed_fp32_peak": achieved / VALU_PEAK_PACKED_TFLOPS}
-        else:
-            achieved = nbytes / avg_s / 1e9
-            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": label,
-                    "avg_launch_ms": dom["avg_ms"], "flops_per_launch": flops, "bytes_per_launch": nbytes}
-    elif dom["bin"] >= 0:
-        bd = bins[dom["bin"]]
-        if bd["class"] == "dft":
-            achieved = bd["flops_per_restart"] * B / avg_s / 1e12
-            roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / VALU_PEAK_TFLOPS, "traffic": None,
-                    "kernel": f"eval bin {dom['bin']} ({bd['class']}, {bd['ct']}, seg {bd['seg']}, "
-                              f"L {bd['L']}, {bd['count']} constraints, len <= {bd['maxk']})",
-                    "avg_launch_ms": dom["avg_ms"],
-                    "frac_of_packed_fp32_peak": achieved / VALU_PEAK_PACKED_TFLOPS}
-        else:
-            achieved = bd["bytes_per_restart"] * B / avg_s / 1e9
-            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                    "kernel": f"eval bin {dom['bin']} ({bd['class']}, len <= {bd['maxk']})",
-                    "avg_launch_ms": dom["avg_ms"]}
-    else:
-        # the gradient reduction: 4 B per literal slot read + 4 B per point read and written
-        nbytes = (4.0 * inst.nnz + 8.0 * inst.n_vars) * B
-        achieved = nbytes / avg_s / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "gradient reduction + step",
-                "avg_launch_ms": dom["avg_ms"], "bytes_per_launch": nbytes}
-    roof["traffic"] = measured_traffic(roof)
-    kernels = []
-    for k in sorted(kern, key=lambda k: -k["total_ms"]):
-        name = "reduce" if k["bin"] == -1 else "grouped eval" if k["bin"] == -2 else (
-            f"bin{k['bin']}:{bins[k['bin']]['class']}/{bins[k['bin']]['ct']}/L{bins[k['bin']]['L']}"
-            f"/k<={bins[k['bin']]['maxk']}")
-        ent = {"kernel": name, "avg_ms": round(k["avg_ms"], 5),
-               "share": round(k["total_ms"] / sum(q["total_ms"] for q in kern), 4)}
-        if k["bin"] >= 0:
-            # algorithmic rates of one bin (launched beside others: shares the chip)
-            bd = bins[k["bin"]]
-            sec = k["avg_ms"] / 1e3
-            ent["alg_GBps"] = round(bd["bytes_per_restart"] * B / sec / 1e9, 1)
-            ent["alg_TFLOPps"] = round(bd["flops_per_restart"] * B / sec / 1e12, 2)
-            ent["constraints"] = bd["count"]
-        kernels.append(ent)
+    t_run = time.perf_counter()
+    head, inst, x_np = measure(args.workload, args, dev, True)
+    print(f"[bench] {args.workload}: {head['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    secondary = {}
+    if not args.no_secondary:
+        for name in ("mixed2000", "large3sat"):
+            if name == args.workload:
+                continue
+            r, _, _ = measure(name, args, dev, False)
+            secondary[name] = r
+            print(f"[bench] {name}: {r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
     res = {
-        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": wl["desc"].format(B=B),
-                   "n_vars": inst.n_vars, "n_cons": inst.m, "nnz": inst.nnz, "restarts": B,
-                   "step": "objective + gradient + exact round-and-check of x_t (one pass), ERWA weight "
-                           "update, projected step",
-                   "iterations_per_graph_replay": chunk,
-                   "eager_events_ms_per_step": (t1 - t0) * 1e3 / args.steps},
-        "roofline": roof,
-        "kernels": kernels,
+        "metric": METRIC, "value": head["value"], "unit": UNIT, "n_gpus": 1, "steps": head["steps"],
+        "warmup": head["warmup"], "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": head["workload"], "n_vars": head["n_vars"], "n_cons": head["n_cons"],
+                   "nnz": head["nnz"], "restarts": head["restarts"],
+                   "step": "objective + gradient + exact round-and-check of x_t (one pass), projected step, "
+                           "ERWA weight update; graph-replayed",
+                   "iterations_per_graph_replay": head["iterations_per_graph_replay"],
+                   "setup_s_incl_autotune": round(head["setup_s_incl_autotune"], 2)},
+        "roofline": head["roofline"],
+        "kernels": head["kernels"],
     }
+    if secondary:
+        res["secondary"] = {k: {"workload": v["workload"], "value": v["value"], "ms_per_step": v["ms_per_step"],
+                                "steps": v["steps"], "roofline": v["roofline"], "kernels": v["kernels"][:6]}
+                            for k, v in secondary.items()}
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(inst, x_np)
-    if not args.no_tts and args.workload == "mixed2000":
+        res["cpu_baseline"] = cpu_baseline(inst, x_np, args.cpu_budget)
+        print(f"[bench] cpu baseline done", file=sys.stderr, flush=True)
+    if not args.no_tts:
         res["time_to_solve"] = time_to_solve()
+    res["bench_seconds"] = round(time.perf_counter() - t_run, 1)
     print(json.dumps(res))
 
 

@@ -220,7 +220,9 @@ ffsat_status ffsat_step_f64(ffsat_plan *plan, double *x, const double *grad,
 /* T fused iterations of (evaluate gradient, projected step with scalar eta)
  * on x (device [n][B], in place), replayed from a captured hipGraph when the
  * plan uses graphs.  F_last (device [B] or NULL) receives the objective at
- * the point the last step started from. */
+ * the point the last step started from.  eta is written to plan-owned
+ * device memory (in stream order) before the steps, so one captured graph
+ * per (x, T, F_last) serves every step size. */
 ffsat_status ffsat_run_steps(ffsat_plan *plan, float *x, int32_t T, float eta, float *F_last,
                              void *stream);
 
@@ -273,8 +275,9 @@ ffsat_status ffsat_vjp(ffsat_plan *plan, const float *grad, const float *con_val
  * when alpha > 0, updates the weights from that iteration's violation counts
  * (as ffsat_erwa_update).  F [B], n_sat [B], U [m] receive the last
  * iteration's values (each optional; U required when alpha > 0).  With
- * graphs enabled the sequence is captured once per argument set and
- * replayed.  Errors as ffsat_eval_step. */
+ * graphs enabled the sequence is captured once per (x, T, alpha > 0, F,
+ * n_sat, U) and replayed; eta and alpha are read from plan-owned device
+ * memory written before each replay.  Errors as ffsat_eval_step. */
 ffsat_status ffsat_run_iters(ffsat_plan *plan, float *x, int32_t T, float eta, float alpha, float *F,
                              int32_t *n_sat, int32_t *U, void *stream);
 
@@ -289,9 +292,14 @@ ffsat_status ffsat_run_iters(ffsat_plan *plan, float *x, int32_t T, float eta, f
  *     F(z) <= F(y) + <g, z - y> + |z - y|^2 / (2 eta), else eta /= 2
  *     (after the last trial z is taken with the halved eta);
  *   t' = (1 + sqrt(1 + 4 t^2)) / 2, y' = z + ((t - 1)/t') (z - x), x' = z.
- * F (optional, [B]) receives F(x') of every restart that moved.  The search
- * reads one counter back to the host per trial (synchronises the stream);
- * the workspace (two [n][B] arrays) is allocated on first use. */
+ * F (optional, [B]) receives F(x') of every restart that moved.  max_ls in
+ * [1, 64].  Nothing is read back to the host: every iteration enqueues a
+ * fixed sequence (the gradient at y and max_ls trial slots); the kernels of
+ * a slot return at once when no restart is still searching, so unneeded
+ * trials cost only their launches.  With graphs enabled the T iterations
+ * are captured once per argument set (buffers, T, max_ls) and replayed.
+ * The workspace (two [n][B] arrays and per-restart scalars) is allocated
+ * on first use. */
 ffsat_status ffsat_fista(ffsat_plan *plan, float *x, float *y, float *eta, float *t, int32_t T,
                          int32_t max_ls, float *F, void *stream);
 

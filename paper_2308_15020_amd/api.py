@@ -276,6 +276,14 @@ class Plan:
         return {"y": x.clone(), "eta": torch.full((self.B,), float(eta0), dtype=torch.float32, device=self.device),
                 "t": torch.ones(self.B, dtype=torch.float32, device=self.device)}
 
+    def fista_reset(self, state: dict, x: torch.Tensor, eta0: float) -> dict:
+        """Restarts a FISTA state in place for the points x (same buffers)."""
+        self._x(x)
+        state["y"].copy_(x)
+        state["eta"].fill_(float(eta0))
+        state["t"].fill_(1.0)
+        return state
+
     def fista(self, x: torch.Tensor, state: dict, T: int, max_ls: int = 15,
               F: Optional[torch.Tensor] = None) -> None:
         """T FISTA iterations with backtracking (ffsat_fista), in place on x and state."""

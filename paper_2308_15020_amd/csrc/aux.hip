@@ -26,6 +26,7 @@ __global__ __launch_bounds__(RED_BLOCK) void k_reduce(ReduceArgs<IO> a, int n_gr
     const int bx = blockIdx.x;
     const int b = blockIdx.y * RED_BLOCK + threadIdx.x;
     if (b >= a.B) return;
+    if (a.skip != nullptr && *a.skip == 0) return;
     const int B = a.B;
     if (bx < n_grad) {
         const int v = bx;
@@ -43,9 +44,12 @@ __global__ __launch_bounds__(RED_BLOCK) void k_reduce(ReduceArgs<IO> a, int n_gr
         for (; e < e1; ++e) acc += (double)a.slot[(size_t)a.vslot[e] * B + b];
         const size_t idx = (size_t)v * B + b;
         if constexpr (STEP) {
-            // same rounding as evaluating the gradient, then the step
+            // same rounding as evaluating the gradient, then the step (step
+            // size from device memory when given: one captured graph serves
+            // every step size)
             const float g = (float)acc;
-            const float y = __builtin_fmaf(-a.eta, g, a.x_step[idx]);
+            const float eta = a.eta_dev != nullptr ? *a.eta_dev : a.eta;
+            const float y = __builtin_fmaf(-eta, g, a.x_step[idx]);
             a.x_step[idx] = fminf(fmaxf(y, -1.0f), 1.0f);
         } else {
             a.grad[idx] = (IO)acc;
@@ -75,6 +79,7 @@ __global__ __launch_bounds__(64) void k_fsum2(ReduceArgs<IO> a, int splits)
 {
     const int b = blockIdx.x * 64 + threadIdx.x;
     if (b >= a.B) return;
+    if (a.skip != nullptr && *a.skip == 0) return;
     if (a.F != nullptr) {
         double acc = 0.0;
 #pragma unroll 8
@@ -194,6 +199,20 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
     if (i < n) p[i] = v;
 }
 
+__global__ void k_set_f32x2(float *p, float a, float b)
+{
+    if (threadIdx.x == 0) {
+        p[0] = a;
+        p[1] = b;
+    }
+}
+
+hipError_t launch_set_f32x2(float *p, float a, float b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_f32x2, dim3(1), dim3(64), 0, s, p, a, b);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
@@ -258,9 +277,11 @@ __device__ __forceinline__ int32_t strided_max(int m, const int32_t *__restrict_
 
 // every block finds the maximum itself (1024 threads, eight loads in
 // flight each), then updates its own 1024 weights
-__global__ __launch_bounds__(1024) void k_erwa_one(int m, const int32_t *__restrict__ U, float *w, float alpha)
+__global__ __launch_bounds__(1024) void k_erwa_one(int m, const int32_t *__restrict__ U, float *w, float alpha,
+                                                   const float *__restrict__ alpha_dev)
 {
     __shared__ int32_t red[16];
+    if (alpha_dev != nullptr) alpha = *alpha_dev;
     const int32_t umax = block_max_1024(strided_max(m, U, threadIdx.x, 1024), red);
     const float inv = umax > 0 ? 1.0f / (float)umax : 0.0f;
     const int c = blockIdx.x * 1024 + threadIdx.x;
@@ -278,9 +299,11 @@ __global__ __launch_bounds__(1024) void k_umax_part(int m, const int32_t *__rest
 }
 
 __global__ __launch_bounds__(1024) void k_erwa_apply(int m, int nparts, const int32_t *__restrict__ part,
-                                                     const int32_t *__restrict__ U, float *w, float alpha)
+                                                     const int32_t *__restrict__ U, float *w, float alpha,
+                                                     const float *__restrict__ alpha_dev)
 {
     __shared__ int32_t red[16];
+    if (alpha_dev != nullptr) alpha = *alpha_dev;
     const int32_t umax = block_max_1024((int)threadIdx.x < nparts ? part[threadIdx.x] : 0, red);
     const float inv = umax > 0 ? 1.0f / (float)umax : 0.0f;
     for (int c = blockIdx.x * 1024 + threadIdx.x; c < m; c += gridDim.x * 1024) {
@@ -289,17 +312,18 @@ __global__ __launch_bounds__(1024) void k_erwa_apply(int m, int nparts, const in
     }
 }
 
-hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, int32_t *part, hipStream_t s)
+hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, const float *alpha_dev, int32_t *part,
+                       hipStream_t s)
 {
     if (m <= ERWA_ONE_BLOCK) {
-        hipLaunchKernelGGL(k_erwa_one, dim3((m + 1023) / 1024), dim3(1024), 0, s, m, U, w, alpha);
+        hipLaunchKernelGGL(k_erwa_one, dim3((m + 1023) / 1024), dim3(1024), 0, s, m, U, w, alpha, alpha_dev);
         return hipGetLastError();
     }
     const int nparts = std::min(1024, (m + 8191) / 8192);
     hipLaunchKernelGGL(k_umax_part, dim3(nparts), dim3(1024), 0, s, m, U, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_erwa_apply, dim3(nparts), dim3(1024), 0, s, m, nparts, part, U, w, alpha);
+    hipLaunchKernelGGL(k_erwa_apply, dim3(nparts), dim3(1024), 0, s, m, nparts, part, U, w, alpha, alpha_dev);
     return hipGetLastError();
 }
 
@@ -431,23 +455,27 @@ namespace ffsat {
 
 constexpr float FISTA_ETA_MIN = 1e-12f;
 
-__global__ void k_fista_begin(int B, const float *__restrict__ eta, int32_t *active, int32_t *searching)
+__global__ void k_fista_begin(int B, const float *__restrict__ eta, int32_t *active, int32_t *searching,
+                              int32_t *n_active)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     const int32_t a = eta[b] >= FISTA_ETA_MIN ? 1 : 0;
     active[b] = a;
     searching[b] = a;
+    if (a) atomicAdd(n_active, 1);
 }
 
 // z = clip(y - eta_b g) for the restarts still searching, and per (chunk of
-// `rows` variables, restart) partial sums of g.(z - y) and |z - y|^2
+// `rows` variables, restart) partial sums of g.(z - y) and |z - y|^2.
+// skip: restarts still searching before this trial (0: nothing to do).
 __global__ __launch_bounds__(256) void k_fista_trial(int n, int B, int rows, int chunks, const float *__restrict__ y,
                                                      const float *__restrict__ g, const float *__restrict__ eta,
-                                                     const int32_t *__restrict__ searching, float *z, float *part)
+                                                     const int32_t *__restrict__ searching, float *z, float *part,
+                                                     const int32_t *__restrict__ skip)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B || !searching[b]) return;
+    if (b >= B || *skip == 0 || !searching[b]) return;
     const float e = eta[b];
     const int v0 = blockIdx.y * rows, v1 = min(n, v0 + rows);
     float dot = 0.f, sq = 0.f;
@@ -466,13 +494,13 @@ __global__ __launch_bounds__(256) void k_fista_trial(int n, int B, int rows, int
 
 // sufficient-decrease test per searching restart; partial sums in a fixed
 // order (FP64); on failure eta halves; after the last trial the point is
-// taken anyway.  pending counts the restarts still searching.
+// taken anyway.  pending counts the restarts still searching after this trial.
 __global__ void k_fista_accept(int B, int chunks, const float *__restrict__ part, const float *__restrict__ Fy,
                                const float *__restrict__ Fz, float *eta, int32_t *searching, float *Fout, int last,
-                               int32_t *pending)
+                               int32_t *pending, const int32_t *__restrict__ skip)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B || !searching[b]) return;
+    if (b >= B || *skip == 0 || !searching[b]) return;
     double dot = 0.0, sq = 0.0;
     for (int c = 0; c < chunks; ++c) {
         dot += (double)part[(size_t)c * B + b];
@@ -524,29 +552,31 @@ int fista_rows(int n, int B)
     return std::min(rows, std::max(n, 1));
 }
 
-hipError_t launch_fista_begin(int B, const float *eta, int32_t *active, int32_t *searching, hipStream_t s)
+hipError_t launch_fista_begin(int B, const float *eta, int32_t *active, int32_t *searching, int32_t *n_active,
+                              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fista_begin, dim3((B + 255) / 256), dim3(256), 0, s, B, eta, active, searching);
+    hipLaunchKernelGGL(k_fista_begin, dim3((B + 255) / 256), dim3(256), 0, s, B, eta, active, searching, n_active);
     return hipGetLastError();
 }
 
 hipError_t launch_fista_trial(int n, int B, const float *y, const float *g, const float *eta, const int32_t *searching,
-                              float *z, float *part, hipStream_t s)
+                              float *z, float *part, const int32_t *skip, hipStream_t s)
 {
     const int rows = fista_rows(n, B);
     const int chunks = (n + rows - 1) / rows;
     hipLaunchKernelGGL(k_fista_trial, dim3((B + 255) / 256, chunks), dim3(256), 0, s, n, B, rows, chunks, y, g, eta,
-                       searching, z, part);
+                       searching, z, part, skip);
     return hipGetLastError();
 }
 
 hipError_t launch_fista_accept(int n, int B, const float *part, const float *Fy, const float *Fz, float *eta,
-                               int32_t *searching, float *Fout, int last, int32_t *pending, hipStream_t s)
+                               int32_t *searching, float *Fout, int last, int32_t *pending, const int32_t *skip,
+                               hipStream_t s)
 {
     const int rows = fista_rows(n, B);
     const int chunks = (n + rows - 1) / rows;
     hipLaunchKernelGGL(k_fista_accept, dim3((B + 255) / 256), dim3(256), 0, s, B, chunks, part, Fy, Fz, eta, searching,
-                       Fout, last, pending);
+                       Fout, last, pending, skip);
     return hipGetLastError();
 }
 

@@ -238,6 +238,58 @@ __device__ __forceinline__ int group_sum_int(int v)
     return v;
 }
 
+// Butterfly product over groups of L lanes (FP64 complex): quad
+// permutations for partners 1 and 2, half-row and row mirrors for 4 and 8
+// (after the earlier stages every lane of a quad / half-row holds the same
+// product, so a mirror reaches the other half), and the gfx950 row swap for
+// 16.  Every lane ends with the product of its group (rounded in its own
+// order).
+template <int CTRL>
+__device__ __forceinline__ void cmul_by_dpp(double &ar, double &ai)
+{
+    const double yr = dpp_f64<CTRL>(ar), yi = dpp_f64<CTRL>(ai);
+    const double nr = fmaT(yr, ar, -yi * ai);
+    const double ni = fmaT(yr, ai, yi * ar);
+    ar = nr;
+    ai = ni;
+}
+// this lane's value and the one of the same lane in the paired row (rows 0-1, 2-3)
+__device__ __forceinline__ void swap_rows16(double v, double &a, double &b)
+{
+    const long long u = __double_as_longlong(v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)(u & 0xffffffffll), (unsigned)(u & 0xffffffffll),
+                                                     false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+    a = __longlong_as_double((long long)lo[0] | ((long long)hi[0] << 32));
+    b = __longlong_as_double((long long)lo[1] | ((long long)hi[1] << 32));
+}
+template <int L>
+__device__ __forceinline__ void allreduce_prod_f64(double &ar, double &ai)
+{
+    if constexpr (L >= 2) cmul_by_dpp<0xB1>(ar, ai);    // quad_perm [1,0,3,2]
+    if constexpr (L >= 4) cmul_by_dpp<0x4E>(ar, ai);    // quad_perm [2,3,0,1]
+    if constexpr (L >= 8) cmul_by_dpp<0x141>(ar, ai);   // row_half_mirror
+    if constexpr (L >= 16) cmul_by_dpp<0x140>(ar, ai);  // row_mirror
+    if constexpr (L >= 32) {
+        double pr, pi, qr, qi;
+        swap_rows16(ar, pr, qr);
+        swap_rows16(ai, pi, qi);
+        // {p, q} = {own, paired row's}: the same product on both rows
+        ar = fmaT(pr, qr, -pi * qi);
+        ai = fmaT(pr, qi, pi * qr);
+    }
+    static_assert(L <= 32, "groups of at most 32 lanes");
+}
+// 1 / v for v in the normal range: hardware estimate and two Newton steps
+__device__ __forceinline__ double recip_f64(double v)
+{
+    double r = __builtin_amdgcn_rcp(v);
+    double e = fmaT(-v, r, 1.0);
+    r = fmaT(r, e, r);
+    e = fmaT(-v, r, 1.0);
+    return fmaT(r, e, r);
+}
+
 // One complex frequency of a constraint: steps i-ii (affine factors psi and
 // their running product), step iii (value term Re(c0 * prod psi)) and the
 // reverse traversal that adds Re(c1 * leave-one-out product) to every
@@ -248,6 +300,10 @@ template <typename CT, int SEG, int L, int FORM>
 __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (&gr)[SEG], const FreqT<CT> &fr,
                                           CT &we)
 {
+    // FP64 bounded-basis frequencies over several lanes: whole product by a
+    // butterfly, then a division (no scans)
+    constexpr bool ALLRED = sizeof(CT) == 8 && L >= 2 && FORM != 3;
+    (void)j;
     const CT tk = fr.tk;
     CT pr[SEG], pi[SEG];
     CT Pr = fr.init, Pi = 0;
@@ -271,17 +327,33 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
             Pr = nr; Pi = ni;
         }
     }
-    CT er, ei, sr, si;
-    group_scan_cplx<CT, L>(j, Pr, Pi, er, ei, sr, si);
-    const CT Gr = fmaT(Pr, sr, -Pi * si);
-    const CT Gi = fmaT(Pr, si, Pi * sr);
-    we += fmaT(fr.c0re, Gr, -fr.c0im * Gi);
+    CT qr, qi;   // product of the other lanes' segments (exclusive prefix times exclusive suffix)
+    if constexpr (ALLRED) {
+        // FP64: every lane forms the whole product with a butterfly and
+        // divides its own segment out.  FP64 products of at most 16
+        // bounded factors stay far from underflow, so the division is
+        // safe; it replaces two 32-lane scans per frequency.
+        CT Tr = Pr, Ti = Pi;
+        allreduce_prod_f64<L>(Tr, Ti);
+        we += fmaT(fr.c0re, Tr, -fr.c0im * Ti);
+        const CT nrm = fmaT(Pr, Pr, Pi * Pi);
+        const CT rinv = recip_f64(nrm);
+        const CT ir = Pr * rinv, ii = -Pi * rinv;
+        qr = fmaT(Tr, ir, -Ti * ii);
+        qi = fmaT(Tr, ii, Ti * ir);
+    } else {
+        CT er, ei, sr, si;
+        group_scan_cplx<CT, L>(j, Pr, Pi, er, ei, sr, si);
+        const CT Gr = fmaT(Pr, sr, -Pi * si);
+        const CT Gi = fmaT(Pr, si, Pi * sr);
+        we += fmaT(fr.c0re, Gr, -fr.c0im * Gi);
+        qr = fmaT(er, sr, -ei * si);
+        qi = fmaT(er, si, ei * sr);
+    }
     // the factors are recomputed from an opaque copy of tk so that the
     // forward products are not kept alive across both passes
     CT tkb = tk;
     asm volatile("" : "+v"(tkb));
-    const CT qr = fmaT(er, sr, -ei * si);
-    const CT qi = fmaT(er, si, ei * sr);
     CT Sr = fmaT(fr.c1re, qr, -fr.c1im * qi);
     CT Si = fmaT(fr.c1re, qi, fr.c1im * qr);
 #pragma unroll
@@ -345,6 +417,7 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
     const int lane = threadIdx.x & 63;
     const int n_chunks = (sp.count + sp.cpw - 1) / sp.cpw;
     if (unit >= n_chunks * sp.n_rb) return;   // whole wave leaves together
+    if (a.skip != nullptr && *a.skip == 0) return;   // uniform: every wave of the launch leaves
     const int chunk = unit / sp.n_rb;
     const int rb = unit - chunk * sp.n_rb;
     const int j = lane & (L - 1);

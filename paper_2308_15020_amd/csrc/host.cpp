@@ -657,6 +657,7 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
         b.maxk = std::max(b.maxk, k);
         b.cost += cost;
         b.lits += k;
+        if (cls == CLASS_DFT) b.k2 += (double)k * (double)k;
     }
 
     // 2. order bins by total cost (heaviest first), constraints by cost inside a bin
@@ -684,6 +685,12 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
 
     Ly.cost_prefix.assign((size_t)m + 1, 0.0);
     for (int q = 0; q < m; ++q) Ly.cost_prefix[(size_t)q + 1] = Ly.cost_prefix[(size_t)q] + items[(size_t)q].cost;
+    Ly.k2_prefix.assign((size_t)m + 1, 0.0);
+    for (int q = 0; q < m; ++q) {
+        const Item &it = items[(size_t)q];
+        const double k2 = bins[(size_t)it.bin].cls == CLASS_DFT ? (double)it.k * (double)it.k : 0.0;
+        Ly.k2_prefix[(size_t)q + 1] = Ly.k2_prefix[(size_t)q] + k2;
+    }
 
     // 3. binned descriptors and literals, original -> binned positions
     std::vector<ConDesc> con((size_t)m);
@@ -1157,7 +1164,8 @@ static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream
 // Splits every bin heavier than an eighth of the total work into
 // cost-balanced contiguous constraint ranges, so that the streams can share
 // the work of one heavy bin.
-static std::vector<Bin> split_bins(const std::vector<Bin> &in, const std::vector<double> &pre)
+static std::vector<Bin> split_bins(const std::vector<Bin> &in, const std::vector<double> &pre,
+                                   const std::vector<double> &k2pre)
 {
     double total = 0;
     for (const Bin &b : in) total += b.cost;
@@ -1187,6 +1195,7 @@ static std::vector<Bin> split_bins(const std::vector<Bin> &in, const std::vector
             part.flops = b.flops * frac;
             part.bytes = b.bytes * frac;
             part.exec_pos = b.exec_pos * frac;
+            part.k2 = k2pre[(size_t)end] - k2pre[(size_t)start];
             part.lits = (int64_t)((double)b.lits * frac);
             out.push_back(part);
             start = end;
@@ -1229,10 +1238,24 @@ static void default_shapes(ffsat_plan *pl)
     }
 }
 
+// Destroys every cached executable graph, each after its latest launch has
+// finished (a replay may still be in flight on the caller's stream).
+static void clear_graphs(ffsat_plan *pl)
+{
+    for (auto &kv : pl->graphs) {
+        if (kv.second.done) {
+            (void)hipEventSynchronize(kv.second.done);
+            (void)hipEventDestroy(kv.second.done);
+        }
+        (void)hipGraphExecDestroy(kv.second.exec);
+    }
+    pl->graphs.clear();
+}
+
 template <typename IO>
 static ffsat_status run_eval(ffsat_plan *pl, const IO *x, IO *F, IO *grad, IO *con_val, int32_t *n_sat,
                              uint32_t *unsat_bits, int32_t *U, bool do_value, float *x_step, float eta,
-                             hipStream_t s);
+                             hipStream_t s, const float *eta_dev = nullptr, const int32_t *skip = nullptr);
 
 // With MODE_AUTO, times one full FP32 evaluation with the fused step (on the
 // tuner's scratch points, step size 0) under each launch structure and keeps
@@ -1369,8 +1392,7 @@ extern "C" ffsat_status ffsat_plan_tune(ffsat_plan *pl, void *stream)
     (void)hipEventDestroy(e1);
     pl->fpart_rows[IO_F32] = fpart_rows_of(pl->bins[IO_F32]);
     // cached graphs baked the old shapes
-    for (auto &kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
-    pl->graphs.clear();
+    clear_graphs(pl);
     pl->tuned = true;
     const size_t n_cached = cache.size();
     if ((st = tune_mode(pl, cache, s)) != FFSAT_OK) return st;
@@ -1388,8 +1410,8 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
     ffsat_plan *pl = new ffsat_plan();
     pl->p = p;
     pl->B = B;
-    pl->bins[0] = split_bins(p->lay[0].bins, p->lay[0].cost_prefix);
-    pl->bins[1] = split_bins(p->lay[1].bins, p->lay[1].cost_prefix);
+    pl->bins[0] = split_bins(p->lay[0].bins, p->lay[0].cost_prefix, p->lay[0].k2_prefix);
+    pl->bins[1] = split_bins(p->lay[1].bins, p->lay[1].cost_prefix, p->lay[1].k2_prefix);
     const int req = opts ? opts->reserved[1] : MODE_AUTO;
     if (req < MODE_AUTO || req > MODE_GROUP_DFT) {
         delete pl;
@@ -1405,6 +1427,7 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
     if (st == FFSAT_OK) {
         hipError_t e = hipMalloc(&pl->d_flag, sizeof(int32_t));
         if (e == hipSuccess) e = hipMalloc(&pl->d_umax, 1024 * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMalloc(&pl->d_hyper, 2 * sizeof(float));
         if (e != hipSuccess) st = fail(FFSAT_E_NOMEM, "hipMalloc flag: %s", hipGetErrorString(e));
     }
     if (st == FFSAT_OK && !(opts && opts->reserved[0] == 1)) {
@@ -1481,7 +1504,8 @@ extern "C" ffsat_status ffsat_plan_destroy(ffsat_plan *pl)
         (void)hipEventDestroy(r.e1);
     }
     for (hipEvent_t e : pl->prof_pool) (void)hipEventDestroy(e);
-    for (auto &kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
+    clear_graphs(pl);
+    (void)hipFree(pl->d_hyper);
     (void)hipFree(pl->d_gent);
     (void)hipFree(pl->d_gblk);
     for (int io = 0; io < 2; ++io) {
@@ -1523,7 +1547,8 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
     o << "{\"B\": " << pl->B << ", \"tuned\": " << (pl->tuned ? "true" : "false") << ", \"mode\": \""
       << mode_names[pl->mode] << "\"" << ", \"mode_auto\": " << (pl->mode_auto ? "true" : "false")
       << ", \"grouped\": " << (pl->grouped && pl->gblocks > 0 ? "true" : "false") << ", \"group_blocks\": " << pl->gblocks
-      << ", \"solo_bins\": " << pl->gsolo.size() << ", \"bins\": {";
+      << ", \"solo_bins\": " << pl->gsolo.size() << ", \"graphs_cached\": " << pl->graphs.size()
+      << ", \"graph_captures\": " << pl->captures << ", \"bins\": {";
     for (int io = 0; io < 2; ++io) {
         o << (io ? ", " : "") << "\"" << (io ? "f64" : "f32") << "\": [";
         for (size_t i = 0; i < pl->bins[io].size(); ++i) {
@@ -1533,6 +1558,7 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
               << ", \"first\": " << b.first << ", \"count\": " << b.count << ", \"maxk\": " << b.maxk
               << ", \"lits\": " << b.lits << ", \"cost\": " << b.cost << ", \"flops_per_restart\": " << b.flops
               << ", \"bytes_per_restart\": " << b.bytes << ", \"positions_per_restart\": " << b.exec_pos
+              << ", \"k2_per_restart\": " << b.k2
               << ", \"cpw\": " << b.cpw
               << ", \"wpb\": " << b.wpb << ", \"fg\": " << b.fg << ", \"in_group\": "
               << ((io == IO_F32 && pl->grouped && pl->gblocks > 0 &&
@@ -1573,7 +1599,7 @@ static ffsat_status check_finite(ffsat_plan *pl, const IO *x, hipStream_t s)
 template <typename IO>
 static ffsat_status run_eval(ffsat_plan *pl, const IO *x, IO *F, IO *grad, IO *con_val, int32_t *n_sat,
                              uint32_t *unsat_bits, int32_t *U, bool do_value, float *x_step, float eta,
-                             hipStream_t s)
+                             hipStream_t s, const float *eta_dev, const int32_t *skip)
 {
     const int io = sizeof(IO) == 4 ? IO_F32 : IO_F64;
     const ffsat_problem *p = pl->p;
@@ -1587,6 +1613,7 @@ static ffsat_status run_eval(ffsat_plan *pl, const IO *x, IO *F, IO *grad, IO *c
     a.want_check = want_check ? 1 : 0;
     a.unsat_bits = unsat_bits;
     a.U = U;
+    a.skip = skip;
     HIPCHK(enqueue_bins<IO>(pl, io, a, s));
     const Layout &Ly = p->lay[io];
     ReduceArgs<IO> r{};
@@ -1599,6 +1626,8 @@ static ffsat_status run_eval(ffsat_plan *pl, const IO *x, IO *F, IO *grad, IO *c
     r.grad = do_value ? grad : nullptr;
     r.x_step = do_value ? x_step : nullptr;
     r.eta = eta;
+    r.eta_dev = eta_dev;
+    r.skip = skip;
     r.fpart = (const IO *)pl->d_fpart[io];
     r.cpart = pl->d_cpart;
     r.rows = pl->fpart_rows[io];
@@ -1680,9 +1709,11 @@ extern "C" ffsat_status ffsat_step_f64(ffsat_plan *pl, double *x, const double *
 
 // The executable graph of a launch sequence, captured once per key on the
 // plan's capture stream (side-stream bins become parallel branches) and kept
-// (at most 16 per plan).
+// (at most 16 per plan; beyond that all are dropped, each after its latest
+// launch has finished).  launch_graph replays it on s and records its
+// completion event.
 template <typename Body>
-static ffsat_status cached_graph(ffsat_plan *pl, const GraphKey &key, Body body, hipGraphExec_t *out)
+static ffsat_status cached_graph(ffsat_plan *pl, const GraphKey &key, Body body, GraphEntry **out)
 {
     auto it = pl->graphs.find(key);
     if (it == pl->graphs.end()) {
@@ -1695,23 +1726,34 @@ static ffsat_status cached_graph(ffsat_plan *pl, const GraphKey &key, Body body,
             if (g) (void)hipGraphDestroy(g);
             return fail(FFSAT_E_HIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
         }
-        hipGraphExec_t ex = nullptr;
-        const hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        GraphEntry ent;
+        const hipError_t e3 = hipGraphInstantiate(&ent.exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e3 != hipSuccess) return fail(FFSAT_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e3));
-        if (pl->graphs.size() >= 16) {
-            for (auto &kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);
-            pl->graphs.clear();
+        const hipError_t e4 = hipEventCreateWithFlags(&ent.done, hipEventDisableTiming);
+        if (e4 != hipSuccess) {
+            (void)hipGraphExecDestroy(ent.exec);
+            return fail(FFSAT_E_HIP, "graph event: %s", hipGetErrorString(e4));
         }
-        it = pl->graphs.emplace(key, ex).first;
+        if (pl->graphs.size() >= 16) clear_graphs(pl);
+        it = pl->graphs.emplace(key, ent).first;
+        ++pl->captures;
     }
-    *out = it->second;
+    *out = &it->second;
     return FFSAT_OK;
 }
 
-static hipError_t enqueue_step_iter(ffsat_plan *pl, float *x, float eta, float *F, hipStream_t s)
+static ffsat_status launch_graph(GraphEntry *g, hipStream_t s)
 {
-    const ffsat_status st = run_eval<float>(pl, x, F, nullptr, nullptr, nullptr, nullptr, nullptr, true, x, eta, s);
+    HIPCHK(hipGraphLaunch(g->exec, s));
+    HIPCHK(hipEventRecord(g->done, s));
+    return FFSAT_OK;
+}
+
+static hipError_t enqueue_step_iter(ffsat_plan *pl, float *x, float *F, hipStream_t s)
+{
+    const ffsat_status st =
+        run_eval<float>(pl, x, F, nullptr, nullptr, nullptr, nullptr, nullptr, true, x, 0.f, s, pl->d_hyper);
     return st == FFSAT_OK ? hipSuccess : hipErrorUnknown;
 }
 
@@ -1724,31 +1766,36 @@ extern "C" ffsat_status ffsat_run_steps(ffsat_plan *pl, float *x, int32_t T, flo
     ffsat_status st = ensure_workspace(pl, IO_F32);
     if (st != FFSAT_OK) return st;
     if ((st = check_finite<float>(pl, x, s)) != FFSAT_OK) return st;
+    // the step size goes to device memory ahead of the (captured) steps
+    HIPCHK(launch_set_f32x2(pl->d_hyper, eta, 0.f, s));
     if (!pl->use_graphs) {
-        for (int t = 0; t < T; ++t) HIPCHK(enqueue_step_iter(pl, x, eta, t == T - 1 ? F_last : nullptr, s));
+        for (int t = 0; t < T; ++t) HIPCHK(enqueue_step_iter(pl, x, t == T - 1 ? F_last : nullptr, s));
         return FFSAT_OK;
     }
-    const GraphKey key{0, x, T, eta, 0.f, F_last, nullptr, nullptr};
-    hipGraphExec_t ex = nullptr;
+    GraphKey key{};
+    key.kind = 0;
+    key.x = x;
+    key.T = T;
+    key.F = F_last;
+    GraphEntry *g = nullptr;
     if ((st = cached_graph(pl, key, [&](hipStream_t cs) {
              hipError_t e = hipSuccess;
              for (int t = 0; t < T && e == hipSuccess; ++t)
-                 e = enqueue_step_iter(pl, x, eta, t == T - 1 ? F_last : nullptr, cs);
+                 e = enqueue_step_iter(pl, x, t == T - 1 ? F_last : nullptr, cs);
              return e;
-         }, &ex)) != FFSAT_OK)
+         }, &g)) != FFSAT_OK)
         return st;
-    HIPCHK(hipGraphLaunch(ex, s));
-    return FFSAT_OK;
+    return launch_graph(g, s);
 }
 
 // T fused iterations: objective, exact check and projected step of x_t, then
 // the adaptive weights from that iteration's violation counts (alpha > 0)
-static hipError_t enqueue_iter(ffsat_plan *pl, float *x, float eta, float alpha, float *F, int32_t *n_sat, int32_t *U,
+static hipError_t enqueue_iter(ffsat_plan *pl, float *x, bool erwa, float *F, int32_t *n_sat, int32_t *U,
                                hipStream_t s)
 {
-    if (run_eval<float>(pl, x, F, nullptr, nullptr, n_sat, nullptr, U, true, x, eta, s) != FFSAT_OK)
+    if (run_eval<float>(pl, x, F, nullptr, nullptr, n_sat, nullptr, U, true, x, 0.f, s, pl->d_hyper) != FFSAT_OK)
         return hipErrorUnknown;
-    if (alpha > 0.f) return launch_erwa(pl->p->m, U, pl->p->d_w, alpha, pl->d_umax, s);
+    if (erwa) return launch_erwa(pl->p->m, U, pl->p->d_w, 0.f, pl->d_hyper + 1, pl->d_umax, s);
     return hipSuccess;
 }
 
@@ -1759,7 +1806,7 @@ static hipError_t enqueue_iter(ffsat_plan *pl, float *x, float eta, float alpha,
 // Evaluation t+1 waits for the weights and the reset; reduction t+1 (which
 // rewrites the level-1 sums) waits for the level-2 sums of t; the caller's
 // stream waits for the side stream at the end.
-static hipError_t enqueue_iters_overlapped(ffsat_plan *pl, float *x, int T, float eta, float alpha, float *F,
+static hipError_t enqueue_iters_overlapped(ffsat_plan *pl, float *x, int T, bool erwa, float *F,
                                            int32_t *n_sat, int32_t *U, hipStream_t s)
 {
     const ffsat_problem *p = pl->p;
@@ -1776,7 +1823,8 @@ static hipError_t enqueue_iters_overlapped(ffsat_plan *pl, float *x, int T, floa
     r.slot = (const float *)pl->d_slot[IO_F32];
     r.grad = nullptr;
     r.x_step = x;
-    r.eta = eta;
+    r.eta = 0.f;
+    r.eta_dev = pl->d_hyper;
     r.fpart = (const float *)pl->d_fpart[IO_F32];
     r.cpart = pl->d_cpart;
     r.rows = pl->fpart_rows[IO_F32];
@@ -1795,7 +1843,7 @@ static hipError_t enqueue_iters_overlapped(ffsat_plan *pl, float *x, int T, floa
         ITER_CHK(enqueue_bins<float>(pl, IO_F32, a, s));
         ITER_CHK(hipEventRecord(pl->ev_eval, s));
         ITER_CHK(hipStreamWaitEvent(q, pl->ev_eval, 0));
-        if (alpha > 0.f) ITER_CHK(launch_erwa(p->m, U, p->d_w, alpha, pl->d_umax, q));
+        if (erwa) ITER_CHK(launch_erwa(p->m, U, p->d_w, 0.f, pl->d_hyper + 1, pl->d_umax, q));
         if (U && t < T - 1) ITER_CHK(launch_fill_i32(U, p->m, 0, q));
         ITER_CHK(hipEventRecord(pl->ev_aux, q));
         if (t > 0) ITER_CHK(hipStreamWaitEvent(s, pl->ev_sum, 0));   // level-2 sums of t-1 read the level-1 rows
@@ -1822,21 +1870,30 @@ extern "C" ffsat_status ffsat_run_iters(ffsat_plan *pl, float *x, int32_t T, flo
     ffsat_status st = ensure_workspace(pl, IO_F32);
     if (st != FFSAT_OK) return st;
     if ((st = check_finite<float>(pl, x, s)) != FFSAT_OK) return st;
+    const bool erwa = alpha > 0.f;
+    // step size and rate go to device memory ahead of the (captured) iterations
+    HIPCHK(launch_set_f32x2(pl->d_hyper, eta, alpha, s));
     auto body = [&](hipStream_t cs) {
-        if (pl->iter_side) return enqueue_iters_overlapped(pl, x, T, eta, alpha, F, n_sat, U, cs);
+        if (pl->iter_side) return enqueue_iters_overlapped(pl, x, T, erwa, F, n_sat, U, cs);
         hipError_t e = hipSuccess;
-        for (int t = 0; t < T && e == hipSuccess; ++t) e = enqueue_iter(pl, x, eta, alpha, F, n_sat, U, cs);
+        for (int t = 0; t < T && e == hipSuccess; ++t) e = enqueue_iter(pl, x, erwa, F, n_sat, U, cs);
         return e;
     };
     if (!pl->use_graphs) {
         HIPCHK(body(s));
         return FFSAT_OK;
     }
-    const GraphKey key{1, x, T, eta, alpha, F, n_sat, U};
-    hipGraphExec_t ex = nullptr;
-    if ((st = cached_graph(pl, key, body, &ex)) != FFSAT_OK) return st;
-    HIPCHK(hipGraphLaunch(ex, s));
-    return FFSAT_OK;
+    GraphKey key{};
+    key.kind = 1;
+    key.x = x;
+    key.T = T;
+    key.opt = erwa ? 1 : 0;
+    key.F = F;
+    key.n_sat = n_sat;
+    key.U = U;
+    GraphEntry *g = nullptr;
+    if ((st = cached_graph(pl, key, body, &g)) != FFSAT_OK) return st;
+    return launch_graph(g, s);
 }
 
 // ------------------------------------------------------------------ check, weights
@@ -1881,9 +1938,11 @@ extern "C" ffsat_status ffsat_erwa_update(ffsat_plan *pl, const int32_t *U, floa
 {
     if (!pl || !U) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
     if (!(alpha >= 0.f && alpha <= 1.f)) return fail(FFSAT_E_INVALID_ARG, "alpha must be in [0, 1]");
-    HIPCHK(launch_erwa(pl->p->m, U, pl->p->d_w, alpha, pl->d_umax, (hipStream_t)stream));
+    HIPCHK(launch_erwa(pl->p->m, U, pl->p->d_w, alpha, nullptr, pl->d_umax, (hipStream_t)stream));
     return FFSAT_OK;
 }
+
+static constexpr int FISTA_MAX_LS = 64;
 
 // FISTA workspace of a plan (first use)
 static ffsat_status ensure_fista(ffsat_plan *pl)
@@ -1899,9 +1958,42 @@ static ffsat_status ensure_fista(ffsat_plan *pl)
     HIPCHK(hipMalloc(&pl->d_fpartial, 2 * chunks * B * sizeof(float)));
     HIPCHK(hipMalloc(&pl->d_fcoef, B * sizeof(float)));
     HIPCHK(hipMalloc(&pl->d_fflags, 2 * B * sizeof(int32_t)));
-    HIPCHK(hipMalloc(&pl->d_fpending, sizeof(int32_t)));
-    pl->device_bytes += (int64_t)((2 * nb + 2 * chunks * B + 3 * B) * sizeof(float) + 2 * B * sizeof(int32_t) + 4);
+    HIPCHK(hipMalloc(&pl->d_fpending, (FISTA_MAX_LS + 1) * sizeof(int32_t)));
+    pl->device_bytes += (int64_t)((2 * nb + 2 * chunks * B + 3 * B) * sizeof(float) + 2 * B * sizeof(int32_t) +
+                                  (FISTA_MAX_LS + 1) * sizeof(int32_t));
     return FFSAT_OK;
+}
+
+// One FISTA iteration per restart (Alg. 5 with backtracking): gradient at y,
+// then max_ls trial slots.  A trial runs only while some restart is still
+// searching: its kernels read the count of searching restarts left by the
+// previous slot (pending[q]) and return at once when it is 0, so the
+// sequence is fixed (graph-capturable, no host read-back) and the trials
+// that are not needed cost only their launches.
+static hipError_t enqueue_fista_iter(ffsat_plan *pl, float *x, float *y, float *eta, float *t, int max_ls, float *F,
+                                     hipStream_t s)
+{
+    const int n = pl->p->n, B = pl->B;
+    int32_t *active = pl->d_fflags, *searching = pl->d_fflags + B;
+    int32_t *pending = pl->d_fpending;   // [max_ls + 1]: [0] active restarts, [q + 1] searching after trial q
+    hipError_t e;
+    if ((e = launch_fill_i32(pending, max_ls + 1, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fista_begin(B, eta, active, searching, pending, s)) != hipSuccess) return e;
+    if (run_eval<float>(pl, y, pl->d_fFy, pl->d_fg, nullptr, nullptr, nullptr, nullptr, true, nullptr, 0.f, s, nullptr,
+                        pending) != FFSAT_OK)
+        return hipErrorUnknown;
+    for (int q = 0; q < max_ls; ++q) {
+        if ((e = launch_fista_trial(n, B, y, pl->d_fg, eta, searching, pl->d_fz, pl->d_fpartial, pending + q, s)) !=
+            hipSuccess)
+            return e;
+        if (run_eval<float>(pl, pl->d_fz, pl->d_fFz, nullptr, nullptr, nullptr, nullptr, nullptr, true, nullptr, 0.f, s,
+                            nullptr, pending + q) != FFSAT_OK)
+            return hipErrorUnknown;
+        if ((e = launch_fista_accept(n, B, pl->d_fpartial, pl->d_fFy, pl->d_fFz, eta, searching, F,
+                                     q == max_ls - 1 ? 1 : 0, pending + q + 1, pending + q, s)) != hipSuccess)
+            return e;
+    }
+    return launch_fista_finish(n, B, active, t, pl->d_fcoef, pl->d_fz, x, y, s);
 }
 
 extern "C" ffsat_status ffsat_fista(ffsat_plan *pl, float *x, float *y, float *eta, float *t, int32_t T,
@@ -1909,35 +2001,34 @@ extern "C" ffsat_status ffsat_fista(ffsat_plan *pl, float *x, float *y, float *e
 {
     if (!pl || !x || !y || !eta || !t) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
     if (T < 0) return fail(FFSAT_E_INVALID_ARG, "T must be >= 0 (got %d)", T);
-    if (max_ls < 1 || max_ls > 64) return fail(FFSAT_E_INVALID_ARG, "max_ls must be in [1, 64] (got %d)", max_ls);
+    if (max_ls < 1 || max_ls > FISTA_MAX_LS)
+        return fail(FFSAT_E_INVALID_ARG, "max_ls must be in [1, %d] (got %d)", FISTA_MAX_LS, max_ls);
+    if (T == 0) return FFSAT_OK;
     hipStream_t s = (hipStream_t)stream;
     ffsat_status st = ensure_workspace(pl, IO_F32);
     if (st != FFSAT_OK) return st;
     if ((st = ensure_fista(pl)) != FFSAT_OK) return st;
-    const int n = pl->p->n, B = pl->B;
-    int32_t *active = pl->d_fflags, *searching = pl->d_fflags + B;
-    for (int it = 0; it < T; ++it) {
-        HIPCHK(launch_fista_begin(B, eta, active, searching, s));
-        if ((st = run_eval<float>(pl, y, pl->d_fFy, pl->d_fg, nullptr, nullptr, nullptr, nullptr, true, nullptr, 0.f,
-                                  s)) != FFSAT_OK)
-            return st;
-        for (int q = 0; q < max_ls; ++q) {
-            HIPCHK(launch_fista_trial(n, B, y, pl->d_fg, eta, searching, pl->d_fz, pl->d_fpartial, s));
-            if ((st = run_eval<float>(pl, pl->d_fz, pl->d_fFz, nullptr, nullptr, nullptr, nullptr, nullptr, true,
-                                      nullptr, 0.f, s)) != FFSAT_OK)
-                return st;
-            HIPCHK(launch_fill_i32(pl->d_fpending, 1, 0, s));
-            HIPCHK(launch_fista_accept(n, B, pl->d_fpartial, pl->d_fFy, pl->d_fFz, eta, searching, F,
-                                       q == max_ls - 1 ? 1 : 0, pl->d_fpending, s));
-            if (q == max_ls - 1) break;
-            int32_t pending = 0;
-            HIPCHK(hipMemcpyAsync(&pending, pl->d_fpending, sizeof pending, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            if (pending == 0) break;
-        }
-        HIPCHK(launch_fista_finish(n, B, active, t, pl->d_fcoef, pl->d_fz, x, y, s));
+    auto body = [&](hipStream_t cs) {
+        hipError_t e = hipSuccess;
+        for (int it = 0; it < T && e == hipSuccess; ++it) e = enqueue_fista_iter(pl, x, y, eta, t, max_ls, F, cs);
+        return e;
+    };
+    if (!pl->use_graphs) {
+        HIPCHK(body(s));
+        return FFSAT_OK;
     }
-    return FFSAT_OK;
+    GraphKey key{};
+    key.kind = 2;
+    key.x = x;
+    key.T = T;
+    key.opt = max_ls;
+    key.F = F;
+    key.y = y;
+    key.eta = eta;
+    key.t = t;
+    GraphEntry *g = nullptr;
+    if ((st = cached_graph(pl, key, body, &g)) != FFSAT_OK) return st;
+    return launch_graph(g, s);
 }
 
 extern "C" ffsat_status ffsat_weight_grad(ffsat_plan *pl, const float *con_val, const float *gF, float *gw,

@@ -62,6 +62,7 @@ struct Bin {
     double flops = 0;           // algorithmic FLOPs per restart (value + gradient)
     double bytes = 0;           // algorithmic HBM bytes per restart (gathers + slot writes)
     double exec_pos = 0;        // literal positions executed per restart (with padding)
+    double k2 = 0;              // sum of k^2 over the bin's root-of-unity constraints
     int cpw = 1, wpb = 4;       // tile shape: constraints per wave, waves per block
     int fg = 1;                 // root-of-unity bins: waves splitting one unit's frequencies
     bool uc = false;            // root-of-unity bin in the unit-circle form (ablation)
@@ -76,6 +77,7 @@ struct Layout {
     int io = IO_F32;
     std::vector<Bin> bins;
     std::vector<double> cost_prefix;   // [m+1] prefix sums of per-constraint cost (binned order)
+    std::vector<double> k2_prefix;     // [m+1] prefix sums of k^2 of root-of-unity constraints (binned order)
     ConDesc *d_con = nullptr;
     int32_t *d_lit = nullptr;    // var | (negated << 31), binned order
     int32_t *d_vptr = nullptr;   // [n+1] variable -> slot CSR
@@ -128,6 +130,7 @@ struct EvalArgs {
     int B, first, count, cpw, n_rb, fpart_row0;
     int want_grad, do_value, want_check, wm;
     int fg;                // root-of-unity bins: waves sharing one unit's frequencies (1, 2 or 4)
+    const int32_t *skip;   // if set and *skip == 0, every wave returns at once (nothing to evaluate)
 };
 
 // A wave's constraint range and tiling (one bin, or one entry of a grouped launch).
@@ -143,16 +146,26 @@ struct GroupEntry {
 // Launch structure of the FP32 evaluation.
 enum { MODE_AUTO = 0, MODE_PER_BIN = 1, MODE_GROUP_ALL = 2, MODE_GROUP_DFT = 3 };
 
+// A captured launch sequence is keyed by its buffers and shape only: step
+// size and weight-update rate are read from device memory (written before
+// each replay), so one graph serves every value.
 struct GraphKey {
-    int32_t kind;          // 0: ffsat_run_steps, 1: ffsat_run_iters
+    int32_t kind;          // 0: ffsat_run_steps, 1: ffsat_run_iters, 2: ffsat_fista
     const void *x;
     int32_t T;
-    float eta, alpha;
+    int32_t opt;           // run_iters: weights updated (alpha > 0); fista: trials per iteration
     const void *F, *n_sat, *U;
+    const void *y, *eta, *t;
     bool operator<(const GraphKey &o) const {
-        return std::tie(kind, x, T, eta, alpha, F, n_sat, U) <
-               std::tie(o.kind, o.x, o.T, o.eta, o.alpha, o.F, o.n_sat, o.U);
+        return std::tie(kind, x, T, opt, F, n_sat, U, y, eta, t) <
+               std::tie(o.kind, o.x, o.T, o.opt, o.F, o.n_sat, o.U, o.y, o.eta, o.t);
     }
+};
+// An executable graph and the event recorded after its latest launch (waited
+// on before the executable is destroyed).
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
 };
 
 }  // namespace ffsat
@@ -205,7 +218,9 @@ struct ffsat_plan {
     bool use_graphs = true;
     bool tuned = false;
     std::string tune_cache;
-    std::map<ffsat::GraphKey, hipGraphExec_t> graphs;
+    std::map<ffsat::GraphKey, ffsat::GraphEntry> graphs;
+    float *d_hyper = nullptr;        // [2] step size and weight-update rate read by captured graphs
+    int64_t captures = 0;            // graphs captured over the plan's life
     int64_t device_bytes = 0;
     bool profiling = false;
     std::vector<ffsat::ProfRec> prof_pending;
@@ -234,6 +249,7 @@ struct ReduceArgs {
     IO *grad;
     float *x_step;
     float eta;
+    const float *eta_dev;   // if set, the step size is read here instead of eta
     const IO *fpart;
     const int32_t *cpart;
     int rows;
@@ -241,6 +257,7 @@ struct ReduceArgs {
     int32_t *ctmp;
     IO *F;
     int32_t *n_sat;
+    const int32_t *skip;   // if set and *skip == 0, the reduction does nothing
 };
 hipError_t launch_reduce_f32(const ReduceArgs<float> &r, hipStream_t s);
 hipError_t launch_reduce_f64(const ReduceArgs<double> &r, hipStream_t s);
@@ -252,7 +269,9 @@ hipError_t launch_step_f64(int64_t total, int B, double *x, const double *g,
                            const double *eta_b, double eta, hipStream_t s);
 hipError_t launch_assign_bits_f32(int n, int B, const float *x, uint32_t *bits, hipStream_t s);
 hipError_t launch_assign_bits_f64(int n, int B, const double *x, uint32_t *bits, hipStream_t s);
-hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, int32_t *part, hipStream_t s);
+hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, const float *alpha_dev, int32_t *part,
+                       hipStream_t s);
+hipError_t launch_set_f32x2(float *p, float a, float b, hipStream_t s);
 hipError_t launch_wgrad(int m, int B, const float *con_val, const float *gF, float *gw,
                         hipStream_t s);
 hipError_t launch_scale_restarts(int64_t total, int B, const float *grad, const float *gF, float *gx,
@@ -265,11 +284,13 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_scratch_points(float *x, int64_t total, uint32_t seed, hipStream_t s);
 hipError_t launch_sat_weight(int m, int B, const uint32_t *bits, const float *w, double *score, hipStream_t s);
 int fista_rows(int n, int B);
-hipError_t launch_fista_begin(int B, const float *eta, int32_t *active, int32_t *searching, hipStream_t s);
+hipError_t launch_fista_begin(int B, const float *eta, int32_t *active, int32_t *searching, int32_t *n_active,
+                              hipStream_t s);
 hipError_t launch_fista_trial(int n, int B, const float *y, const float *g, const float *eta, const int32_t *searching,
-                              float *z, float *part, hipStream_t s);
+                              float *z, float *part, const int32_t *skip, hipStream_t s);
 hipError_t launch_fista_accept(int n, int B, const float *part, const float *Fy, const float *Fz, float *eta,
-                               int32_t *searching, float *Fout, int last, int32_t *pending, hipStream_t s);
+                               int32_t *searching, float *Fout, int last, int32_t *pending, const int32_t *skip,
+                               hipStream_t s);
 hipError_t launch_fista_finish(int n, int B, const int32_t *active, float *t, float *coef, const float *z, float *x,
                                float *y, hipStream_t s);
 

@@ -47,7 +47,8 @@ class Search:
                  weighting: bool = True, policy: str = "ROF", x0: Optional[torch.Tensor] = None, seed: int = 0,
                  plan: Optional[Plan] = None, optimizer: str = "pgd", max_ls: int = 15,
                  maximize: Optional[np.ndarray] = None, step_norm: bool = True,
-                 random_phase: Optional[Callable[[int], torch.Tensor]] = None):
+                 random_phase: Optional[Callable[[int], torch.Tensor]] = None,
+                 x_buf: Optional[torch.Tensor] = None):
         if optimizer not in ("pgd", "fista"):
             raise ValueError("optimizer must be 'pgd' or 'fista'")
         if not policy or any(ph not in PHASE_MODE for ph in policy):
@@ -60,11 +61,14 @@ class Search:
         dev = problem.device
         self.plan = plan or Plan(problem, B)
         problem.set_weights(np.ones(problem.m, dtype=np.float32))
+        # the iterate lives in x_buf when given: the library's captured step
+        # graphs are keyed by the buffers, so searches that share x_buf on
+        # one plan replay the same graph
+        self.x = x_buf if x_buf is not None else torch.empty(problem.n, B, dtype=torch.float32, device=dev)
         if x0 is None:
-            self.x = torch.empty(problem.n, B, dtype=torch.float32, device=dev)
             self.plan.rephase(self.x, PHASE_MODE["R"], seed=seed)
         else:
-            self.x = x0.detach().to(dev, torch.float32).contiguous().clone()
+            self.x.copy_(x0.detach().to(dev, torch.float32))
         self.state = self.plan.fista_state(self.x, eta) if optimizer == "fista" else None
         self.w_score = None if maximize is None else torch.as_tensor(np.asarray(maximize, np.float32), device=dev)
         self.best_w, self.best_assign = None, None
@@ -110,7 +114,8 @@ class Search:
         else:
             self.plan.rephase(self.x, PHASE_MODE[phase], seed=self.seed * 1000003 + r + 1)
         if self.state is not None:
-            self.state = self.plan.fista_state(self.x, self.eta)
+            # in place: the same state buffers keep the captured FISTA graph
+            self.plan.fista_reset(self.state, self.x, self.eta)
 
 
 def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: float = 0.05,
@@ -118,7 +123,8 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
           x0: Optional[torch.Tensor] = None, seed: int = 0, time_limit: Optional[float] = None,
           plan: Optional[Plan] = None, log: bool = False, optimizer: str = "pgd",
           max_ls: int = 15, maximize: Optional[np.ndarray] = None, step_norm: bool = True,
-          random_phase: Optional[Callable[[int], torch.Tensor]] = None) -> SolveResult:
+          random_phase: Optional[Callable[[int], torch.Tensor]] = None,
+          x_buf: Optional[torch.Tensor] = None) -> SolveResult:
     """Alg. 1: returns at the first round in which some restart's rounded point
     satisfies every constraint (decided by the exact checker).
 
@@ -137,6 +143,8 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
     The search itself still uses the problem's (adaptive) weights.
     random_phase: draws the points of the random phase after failed round r
     (default: U[-1, 1] from the library), e.g. a fresh learned proposal.
+    x_buf: a [n][B] float32 device buffer to hold the iterate (its pointer
+    keys the captured step graph, so runs sharing it replay one graph).
     step_norm: with adaptive weights, divide the projected step size by the
     mean weight after every update (the weights shrink towards U/max U, which
     would otherwise shorten a fixed step; the paper's line search adapts the
@@ -147,7 +155,7 @@ def solve(problem: Problem, B: int = 256, rounds: int = 100, T: int = 50, eta: f
     m = problem.m
     S = Search(problem, B, T=T, eta=eta, alpha=alpha, weighting=weighting, policy=policy, x0=x0, seed=seed,
                plan=plan, optimizer=optimizer, max_ls=max_ls, maximize=maximize, step_norm=step_norm,
-               random_phase=random_phase)
+               random_phase=random_phase, x_buf=x_buf)
     best = -1
     for r in range(rounds):
         b, cur = S.run_round()

@@ -344,6 +344,61 @@ def hidden2_ksat(n: int, seed: int, ratio: float = 4.26, k: int = 3, name="") ->
     return assemble(n, [(KIND_OR, np.zeros(m, np.int32), rows)], name=name or f"hidden2-{k}sat-n{n}"), sigma
 
 
+def hidden2_hybrid(n: int, seed: int, *, n_or=0, or_len=(3, 3), n_xor=0, xor_len=(3, 3),
+                   n_card=0, card_len=(10, 10), name="") -> tuple:
+    """A hybrid formula satisfied by a hidden assignment sigma whose literal
+    counts carry no hint of sigma (the 2-hidden idea of hidden2_ksat carried
+    over to mixed formulas):
+      * OR clauses with Bernoulli(1/2) signs are kept only if both sigma and
+        its complement satisfy them (some literal true and some false);
+      * XOR constraints over positive literals take the parity of sigma;
+      * at-least-t constraints have all-positive or all-negative literals
+        with probability 1/2 each, drawn independently of sigma, and
+        t ~ U{1..floor(len/2)} redrawn from U{1..c} when sigma makes only
+        c < t of its literals true (c = 0: the sign is redrawn).
+    Returns (Instance, sigma bool[n], True = True)."""
+    rng = np.random.default_rng(seed)
+    sigma = rng.random(n) < 0.5
+    groups = []
+
+    def lit_true(lits):
+        v = np.abs(lits) - 1
+        return np.where(lits > 0, sigma[v], ~sigma[v])
+
+    if n_or:
+        lens = rng.integers(or_len[0], or_len[1] + 1, size=n_or)
+        rows = []
+        for k in lens:
+            while True:
+                v = rng.choice(n, size=int(k), replace=False)
+                neg = rng.random(int(k)) < 0.5
+                r = np.where(neg, -(v + 1), v + 1).astype(np.int32)
+                tr = lit_true(r)
+                if tr.any() and not tr.all():
+                    rows.append(r)
+                    break
+        groups.append((KIND_OR, np.zeros(n_or, np.int32), rows))
+    if n_xor:
+        _, rows = _draw_group(rng, n, n_xor, xor_len[0], xor_len[1], "positive")
+        par = np.array([int(lit_true(r).sum() % 2) for r in rows])
+        groups.append((KIND_XOR, par, rows))
+    if n_card:
+        lens, rows = _draw_group(rng, n, n_card, card_len[0], card_len[1], "uniform_block")
+        ts = []
+        for i, r in enumerate(rows):
+            cnt = int(lit_true(r).sum())
+            while cnt == 0:
+                r = -r
+                rows[i] = r
+                cnt = int(lit_true(r).sum())
+            t = int(rng.integers(1, max(1, r.size // 2) + 1))
+            if t > cnt:
+                t = int(rng.integers(1, cnt + 1))
+            ts.append(t)
+        groups.append((KIND_CARD, np.array(ts), rows))
+    return assemble(n, groups, name=name or f"hidden2-hybrid-n{n}"), sigma
+
+
 def maxcut_planted(n: int, seed: int, p_in: float = 0.1, p_out: float = 0.3, w_in: float = 1.0,
                    w_out: float = 2.0) -> Instance:
     """Weighted Max-Cut on a planted two-part graph as weighted 2-XOR: edge
