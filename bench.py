@@ -55,7 +55,7 @@ OPS_PER_K2 = 10.0                              # root-of-unity work per (constra
 WORKLOADS = {
     "large": {"gen": "config3", "seed": 3000, "B": 256, "steps": 30, "warmup": 3,
               "desc": "large hybrid SAT n=100000: 420000 3-SAT, 10000 XOR (len 8-64), 2000 at-least-t "
-                      "(len 128-512, t ~ U{1..len/2}; FP64 root-of-unity products beyond 256 literals), "
+                      "(len 128-512, t ~ U{{1..len/2}}; FP64 root-of-unity products beyond 256 literals), "
                       "{B} restarts, FP32"},
     "mixed2000": {"gen": "config2", "seed": 2000, "B": 1024, "steps": 200, "warmup": 20,
                   "desc": "mixed hybrid SAT n=2000: 8000 OR (len 3-7), 500 XOR (len 3-20), "
