@@ -118,7 +118,16 @@ typedef struct {
                                 autotuner times the others and keeps the fastest),
                                 1 one launch per bin, 2 one grouped launch for all
                                 bins, 3 a grouped launch for the root-of-unity bins
-                                with the others beside it; others must be 0 */
+                                with the others beside it; reserved[2]: gradient of
+                                the transform-free constraints of length <= 7
+                                (OR, AND, XOR, constants), 0 automatic (the
+                                autotuner decides; off without it), 1 through
+                                per-literal slots and the slot reduction, 2 gathered
+                                per variable for lengths <= 7, 3 for lengths <= 3
+                                (the pulled gradient; never with launch structure 2,
+                                never for n * B above 2^29); reserved[3]:
+                                variables per wave of the pulled gradient, 0..8
+                                (0 = 8); others must be 0 */
 } ffsat_plan_opts;
 
 /* ---- errors ------------------------------------------------------------- */

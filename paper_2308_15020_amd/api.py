@@ -102,7 +102,8 @@ class Plan:
     """A batch size B bound to a problem, with its device workspace."""
 
     def __init__(self, problem: Problem, B: int, autotune: bool = False, use_graphs: bool = True,
-                 tune_cache: Optional[str] = None, side_streams: bool = True, mode: str = "auto"):
+                 tune_cache: Optional[str] = None, side_streams: bool = True, mode: str = "auto",
+                 pull: str = "auto", pull_vc: int = 0):
         self.problem = problem
         self.B = int(B)
         self.device = problem.device
@@ -115,6 +116,14 @@ class Plan:
         if mode not in modes:
             raise ValueError(f"mode must be one of {sorted(modes)}")
         o.reserved[1] = modes[mode]
+        # gradient of the short transform-free constraints gathered per variable
+        # ("le3": length <= 3, "le7": <= 7) instead of through slots ("off");
+        # "auto": chosen by the autotuner (off without it)
+        pulls = {"auto": 0, "off": 1, "le7": 2, "le3": 3}
+        if pull not in pulls:
+            raise ValueError(f"pull must be one of {sorted(pulls)}")
+        o.reserved[2] = pulls[pull]
+        o.reserved[3] = int(pull_vc)
         h = C.c_void_p()
         check(lib().ffsat_plan_create(problem.handle, self.B, C.byref(o), C.byref(h)))
         self._h = h

@@ -635,9 +635,12 @@ struct EvalFn {
     explicit operator bool() const { return fn != nullptr; }
 };
 
-// Segment shapes: L = 1 with SEG in {4, 8, ..., SMAX}; L >= 2 with SEG in
-// (SMAX/2, SMAX], multiples of 4 (SMAX = 32 for FP32 arithmetic, 16 for FP64),
-// and SEG = 16 at every L.
+// Segment shapes.  FP32 arithmetic: L = 1 with SEG in {4, 8, ..., 32}, L >= 2
+// with SEG in {16, 20, 24, 28, 32}.  FP64 arithmetic: L = 1 with SEG in
+// {4, 8, ..., 24}; L = 2..8 with SEG in {16, 20, 24}; L = 16 with every even
+// SEG from 14 to 24 and L = 32 with SEG 14 or 16 (the long root-of-unity
+// bins, where a padding position costs as much as a literal in every
+// frequency).
 template <typename IO, typename CT, int SEG, int L, bool CPLX>
 static EvalFn<IO> handle()
 {
@@ -650,15 +653,19 @@ static EvalFn<IO> handle()
 template <typename IO, typename CT, bool CPLX, int L>
 static EvalFn<IO> pick_L(int seg)
 {
+    constexpr bool F64 = sizeof(CT) == 8;
     switch (seg) {
     case 4: if constexpr (L == 1) return handle<IO, CT, 4, L, CPLX>(); break;
     case 8: if constexpr (L == 1) return handle<IO, CT, 8, L, CPLX>(); break;
-    case 12: if constexpr (L == 1 || sizeof(CT) == 8) return handle<IO, CT, 12, L, CPLX>(); break;
+    case 12: if constexpr (L == 1) return handle<IO, CT, 12, L, CPLX>(); break;
+    case 14: if constexpr (F64 && L >= 16) return handle<IO, CT, 14, L, CPLX>(); break;
     case 16: return handle<IO, CT, 16, L, CPLX>();
-    case 20: if constexpr (sizeof(CT) == 4) return handle<IO, CT, 20, L, CPLX>(); break;
-    case 24: if constexpr (sizeof(CT) == 4) return handle<IO, CT, 24, L, CPLX>(); break;
-    case 28: if constexpr (sizeof(CT) == 4) return handle<IO, CT, 28, L, CPLX>(); break;
-    case 32: if constexpr (sizeof(CT) == 4) return handle<IO, CT, 32, L, CPLX>(); break;
+    case 18: if constexpr (F64 && L == 16) return handle<IO, CT, 18, L, CPLX>(); break;
+    case 20: if constexpr (!F64 || L <= 16) return handle<IO, CT, 20, L, CPLX>(); break;
+    case 22: if constexpr (F64 && L == 16) return handle<IO, CT, 22, L, CPLX>(); break;
+    case 24: if constexpr (!F64 || L <= 16) return handle<IO, CT, 24, L, CPLX>(); break;
+    case 28: if constexpr (!F64) return handle<IO, CT, 28, L, CPLX>(); break;
+    case 32: if constexpr (!F64) return handle<IO, CT, 32, L, CPLX>(); break;
     default: break;
     }
     return EvalFn<IO>{};

@@ -134,6 +134,22 @@ TypeD real_and() { TypeD t; t.has_real = 1; t.alpha = 0.5; t.beta = -0.5; t.c0r 
 TypeD real_xor(int p) { TypeD t; t.has_real = 1; t.alpha = 0; t.beta = 1; t.c0r = t.c1r = (p & 1) ? 1.0 : -1.0; t.cst = 0; t.pad = 1; return t; }
 TypeD real_const(double v) { TypeD t; t.cst = v; t.pad = 1; return t; }
 
+// Factor, value and gradient coefficients of every transform-free kind (the
+// same constants as the slot path's type tables), laid out for k_pull.
+static std::vector<float> rkind_table()
+{
+    const TypeD t[RKIND_N] = {real_or(), real_and(), real_xor(1), real_xor(0), real_const(-1.0), real_const(1.0)};
+    std::vector<float> r(RK_TABLE, 0.f);
+    for (int i = 0; i < RKIND_N; ++i) {
+        r[(size_t)i] = (float)t[i].alpha;
+        r[(size_t)8 + i] = (float)t[i].beta;
+        r[(size_t)16 + i] = t[i].has_real ? (float)t[i].c0r : 0.f;
+        r[(size_t)24 + i] = t[i].has_real ? (float)t[i].c1r : 0.f;
+        r[(size_t)32 + i] = (float)t[i].cst;
+    }
+    return r;
+}
+
 // Root-of-unity evaluation of a symmetric constraint (Alg. 2), with the
 // factor of literal i at frequency a taken in the bounded basis
 //   q_i + p_i z = (1+z)/2 + l_i (1-z)/2,  z = exp(2 pi i a / N)
@@ -417,17 +433,30 @@ void shape_for_uc(int k, int &seg, int &L)
 }
 
 // Segment shape of a constraint of length k: L lanes (a power of two) of SEG
-// positions each (4, 8, 16 or 24 for FP32 arithmetic, 32 past k = 384;
-// 4, 8, 12 or 16 for FP64), L * SEG >= k, the smallest such L and then the
-// smallest SEG.  Fewer distinct shapes mean fewer, larger kernel launches.
+// positions each, L * SEG >= k, the smallest such L and then the smallest
+// SEG.  FP32 arithmetic: SEG in {4, 8, 16, 24} (32 past k = 384).  FP64
+// arithmetic: SEG up to 24 (multiples of 4 below 16 lanes), 16-lane groups
+// take every even SEG from 14 to 24 and 32-lane groups (k > 384) 14 or 16:
+// in the long root-of-unity bins a padding position costs as much as a
+// literal in every frequency, and each doubling of L adds a butterfly stage
+// per frequency.  Fewer distinct shapes mean fewer, larger kernel launches.
 void shape_for(int ct, int k, int &seg, int &L)
 {
+    if (ct == CT_F64) {
+        L = 1;
+        while ((k + L - 1) / L > 24 && L < 32) L <<= 1;
+        const int s = (k + L - 1) / L;
+        if (L >= 16) seg = std::max(14, ((s + 1) / 2) * 2);
+        else if (L > 1) seg = std::max(16, ((s + 3) / 4) * 4);
+        else seg = s <= 4 ? 4 : ((s + 3) / 4) * 4;
+        return;
+    }
     // FP32: segments of at most 24 literals (the register budget of 3+ waves
     // per SIMD), 32 only where 16 lanes of 24 do not reach (k > 384)
-    int smax = ct == CT_F32 ? 24 : 16;
+    int smax = 24;
     L = 1;
     while ((k + L - 1) / L > smax) {
-        if (ct == CT_F32 && L == 16) {
+        if (L == 16) {
             smax = 32;
             break;
         }
@@ -436,8 +465,7 @@ void shape_for(int ct, int k, int &seg, int &L)
     const int s = (k + L - 1) / L;
     if (s <= 4) seg = 4;
     else if (s <= 8) seg = 8;
-    else if (ct == CT_F32) seg = ((s + 7) / 8) * 8;   // 16, 24 (32 only past k = 384)
-    else seg = ((s + 3) / 4) * 4;
+    else seg = ((s + 7) / 8) * 8;   // 16, 24 (32 only past k = 384)
 }
 
 struct TypeKey {
@@ -555,7 +583,76 @@ static void free_layout(Layout &L)
     (void)hipFree(L.d_t64);
     (void)hipFree(L.d_f32);
     (void)hipFree(L.d_f64);
+    for (PullLayout &P : L.pull) {
+        (void)hipFree(P.d_pptr);
+        (void)hipFree(P.d_pent);
+        (void)hipFree(P.d_vptr);
+        (void)hipFree(P.d_vslot);
+        (void)hipFree(P.d_rk);
+    }
     L = Layout();
+}
+
+// The pulled-occurrence lists of pull class c (constraints of the FP32
+// layout's bins with pk >= c): per variable, ascending (binned constraint,
+// position), one entry {original constraint, meta, the other literals in
+// constraint order, padded with the variable itself}; and the
+// variable-major transpose of every other slot.  Built once per class.
+static ffsat_status build_pull(ffsat_problem *p, int c)
+{
+    Layout &Ly = p->lay[IO_F32];
+    PullLayout &P = Ly.pull[c];
+    if (P.built) return FFSAT_OK;
+    const int E = PULL_E[c];
+    const int n = p->n, m = p->m;
+    std::vector<char> pulled((size_t)m, 0);
+    for (const Bin &b : Ly.bins)
+        if (b.pk >= c)
+            for (int q = b.first; q < b.first + b.count; ++q) pulled[(size_t)q] = 1;
+    std::vector<int32_t> pptr((size_t)n + 1, 0), vptr((size_t)n + 1, 0);
+    for (int q = 0; q < m; ++q) {
+        const ConDesc &d = Ly.h_con[(size_t)q];
+        for (int i = 0; i < d.k; ++i) {
+            const int v = Ly.h_lit[(size_t)d.off + i] & 0x7fffffff;
+            (pulled[(size_t)q] ? pptr : vptr)[(size_t)v + 1]++;
+        }
+    }
+    for (int v = 0; v < n; ++v) {
+        pptr[(size_t)v + 1] += pptr[(size_t)v];
+        vptr[(size_t)v + 1] += vptr[(size_t)v];
+    }
+    std::vector<int32_t> pent((size_t)pptr[(size_t)n] * E), vslot((size_t)vptr[(size_t)n]);
+    std::vector<int32_t> pfill(pptr.begin(), pptr.end() - 1), vfill(vptr.begin(), vptr.end() - 1);
+    for (int q = 0; q < m; ++q) {
+        const ConDesc &d = Ly.h_con[(size_t)q];
+        const int32_t *cl = &Ly.h_lit[(size_t)d.off];
+        if (!pulled[(size_t)q]) {
+            for (int i = 0; i < d.k; ++i) vslot[(size_t)vfill[(size_t)(cl[i] & 0x7fffffff)]++] = d.off + i;
+            continue;
+        }
+        const int rk = Ly.h_rk[(size_t)q];
+        if (rk < 0 || d.k > PULL_K[c]) return fail(FFSAT_E_HIP, "pull layout: constraint %d is not pullable", d.orig);
+        const int chk = std::min(std::max(d.chk, -2), d.k + 1);   // counts never exceed k
+        for (int i = 0; i < d.k; ++i) {
+            const int v = cl[i] & 0x7fffffff;
+            int32_t *ent = &pent[(size_t)pfill[(size_t)v]++ * E];
+            ent[0] = d.orig;
+            ent[1] = rk | ((d.k - 1) << 3) | ((chk + 2) << 6) | ((cl[i] < 0 ? 1 : 0) << 10) | ((i == 0 ? 1 : 0) << 11);
+            int t = 2;
+            for (int j = 0; j < d.k; ++j)
+                if (j != i) ent[t++] = cl[j];
+            while (t < E) ent[t++] = v;
+        }
+    }
+    ffsat_status st;
+    if ((st = upload(&P.d_pptr, pptr, p->device_bytes)) != FFSAT_OK) return st;
+    if (!pent.empty() && (st = upload(&P.d_pent, pent, p->device_bytes)) != FFSAT_OK) return st;
+    if ((st = upload(&P.d_vptr, vptr, p->device_bytes)) != FFSAT_OK) return st;
+    if (!vslot.empty() && (st = upload(&P.d_vslot, vslot, p->device_bytes)) != FFSAT_OK) return st;
+    if ((st = upload(&P.d_rk, rkind_table(), p->device_bytes)) != FFSAT_OK) return st;
+    P.n_ent = pptr[(size_t)n];
+    P.built = true;
+    return FFSAT_OK;
 }
 
 using CoeffMemo = std::map<std::tuple<int, int, int>, std::vector<cld>>;
@@ -574,9 +671,12 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
     struct Item { int c, k, type, bin; double cost; };
     std::vector<Item> items((size_t)m);
     struct BinKey {
-        int cls, ct, seg, L;
-        bool operator<(const BinKey &o) const { return std::tie(cls, ct, seg, L) < std::tie(o.cls, o.ct, o.seg, o.L); }
+        int cls, ct, seg, L, pk;
+        bool operator<(const BinKey &o) const {
+            return std::tie(cls, ct, seg, L, pk) < std::tie(o.cls, o.ct, o.seg, o.L, o.pk);
+        }
     };
+    std::vector<int8_t> rkind((size_t)m, -1);   // original order
     std::map<BinKey, int> bin_index;
     std::vector<Bin> bins;
     for (int c = 0; c < m; ++c) {
@@ -625,12 +725,20 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
         } else {
             ti = it->second;
         }
-        BinKey bk{cls, ct, seg, L};
+        // pull class (FP32 layout): transform-free chains of length <= 3, 4..7
+        const int pk = (io == IO_F32 && cls == CLASS_REAL && L == 1 && k <= PULL_K[PULL_LE7])
+                           ? (k <= PULL_K[PULL_LE3] ? PULL_LE3 : PULL_LE7) : 0;
+        if (cls == CLASS_REAL) {
+            rkind[(size_t)c] = (int8_t)(rk == RK_OR ? RKIND_OR : rk == RK_AND ? RKIND_AND
+                                        : rk == RK_XOR ? (rparam ? RKIND_XOR_ODD : RKIND_XOR_EVEN)
+                                        : (rparam < 0 ? RKIND_TRUE : RKIND_FALSE));
+        }
+        BinKey bk{cls, ct, seg, L, pk};
         auto bi = bin_index.find(bk);
         int bidx;
         if (bi == bin_index.end()) {
             Bin b;
-            b.cls = cls; b.ct = ct; b.seg = seg; b.L = L;
+            b.cls = cls; b.ct = ct; b.seg = seg; b.L = L; b.pk = pk;
             b.uc = uc && cls == CLASS_DFT;
             bidx = (int)bins.size();
             bins.push_back(b);
@@ -660,10 +768,15 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
         if (cls == CLASS_DFT) b.k2 += (double)k * (double)k;
     }
 
-    // 2. order bins by total cost (heaviest first), constraints by cost inside a bin
+    // 2. order bins by pull class (pullable bins last, so that their objective
+    // rows are the last rows), then by total cost (heaviest first);
+    // constraints by cost inside a bin (transform-free: longest first)
     std::vector<int> border(bins.size());
     for (size_t i = 0; i < bins.size(); ++i) border[i] = (int)i;
-    std::stable_sort(border.begin(), border.end(), [&](int a, int b) { return bins[a].cost > bins[b].cost; });
+    std::stable_sort(border.begin(), border.end(), [&](int a, int b) {
+        if (bins[a].pk != bins[b].pk) return bins[a].pk < bins[b].pk;
+        return bins[a].cost > bins[b].cost;
+    });
     std::vector<int> rank(bins.size());
     for (size_t r = 0; r < border.size(); ++r) rank[(size_t)border[r]] = (int)r;
     std::stable_sort(items.begin(), items.end(), [&](const Item &a, const Item &b) {
@@ -696,9 +809,11 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
     std::vector<ConDesc> con((size_t)m);
     std::vector<int32_t> lit((size_t)p->nnz);
     std::vector<int32_t> pos((size_t)m);
+    Ly.h_rk.assign((size_t)m, -1);
     int64_t off = 0;
     for (int q = 0; q < m; ++q) {
         const Item &it = items[(size_t)q];
+        Ly.h_rk[(size_t)q] = rkind[(size_t)it.c];
         const int kd = d->kinds[it.c], pm = d->params[it.c];
         const int chk = kd == FFSAT_KIND_OR ? 1 : (kd == FFSAT_KIND_XOR ? ((pm & 1) ? -2 : -1) : std::max(pm, 0));
         con[(size_t)q] = ConDesc{(int32_t)off, it.k, it.type, it.c, chk, 0, 0, 0};
@@ -744,6 +859,10 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
     ffsat_status st;
     if ((st = upload(&Ly.d_con, con, p->device_bytes)) != FFSAT_OK) return st;
     if ((st = upload(&Ly.d_lit, lit, p->device_bytes)) != FFSAT_OK) return st;
+    if (io == IO_F32) {
+        Ly.h_con = con;
+        Ly.h_lit = lit;
+    }
     if ((st = upload(&Ly.d_vptr, vptr, p->device_bytes)) != FFSAT_OK) return st;
     if ((st = upload(&Ly.d_vslot, vslot, p->device_bytes)) != FFSAT_OK) return st;
     if ((st = upload(&Ly.d_pos, pos, p->device_bytes)) != FFSAT_OK) return st;
@@ -862,16 +981,19 @@ static ffsat_status ensure_workspace(ffsat_plan *pl, int io)
     if (pl->d_slot[io]) return FFSAT_OK;
     const size_t es = io == IO_F32 ? sizeof(float) : sizeof(double);
     const size_t B = (size_t)pl->B;
+    // objective / count rows: at most one per constraint, plus one per
+    // variable chunk of the pulled gradient
+    const int max_rows = pl->p->m + pl->p->n;
     const size_t slot = (size_t)pl->p->nnz * B * es;
-    const size_t fpart = (size_t)pl->p->m * B * es;
-    const size_t ftmp = (size_t)f_splits(pl->p->m) * B * es;
+    const size_t fpart = (size_t)max_rows * B * es;
+    const size_t ftmp = (size_t)f_splits(max_rows) * B * es;
     HIPCHK(hipMalloc(&pl->d_slot[io], slot));
     HIPCHK(hipMalloc(&pl->d_fpart[io], fpart));
     HIPCHK(hipMalloc(&pl->d_ftmp[io], ftmp));
     pl->device_bytes += (int64_t)(slot + fpart + ftmp);
     if (!pl->d_cpart) {
-        const size_t cp = (size_t)pl->p->m * B * sizeof(int32_t);
-        const size_t ct = (size_t)f_splits(pl->p->m) * B * sizeof(int32_t);
+        const size_t cp = (size_t)max_rows * B * sizeof(int32_t);
+        const size_t ct = (size_t)f_splits(max_rows) * B * sizeof(int32_t);
         HIPCHK(hipMalloc(&pl->d_cpart, cp));
         HIPCHK(hipMalloc(&pl->d_ctmp, ct));
         pl->device_bytes += (int64_t)(cp + ct);
@@ -1062,8 +1184,11 @@ static ffsat_status build_groups(ffsat_plan *pl)
 // spread over them (heaviest first, each to the least loaded stream) after a
 // fork event on s, and s waits for all of them: independent bins overlap,
 // and under graph capture they become parallel branches.
+// Bins of pull class >= pk_limit are skipped (their gradient, objective and
+// check come from k_pull); they are the last bins, so the launched bins'
+// objective rows are the first rows either way.
 template <typename IO>
-static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream_t s)
+static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream_t s, int pk_limit = 3)
 {
     const Layout &Ly = pl->p->lay[io];
     const std::vector<Bin> &bins = pl->bins[io];
@@ -1081,6 +1206,7 @@ static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream
             }
             for (int bi : pl->gsolo) {
                 const Bin &b = bins[bi];
+                if (b.pk >= pk_limit) continue;
                 int row0 = 0;
                 for (int q = 0; q < bi; ++q) row0 += (bins[q].count + bins[q].cpw - 1) / bins[q].cpw;
                 a.first = b.first;
@@ -1122,6 +1248,7 @@ static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream
     int row0 = 0;
     int bi = 0;
     for (const Bin &b : bins) {
+        if (b.pk >= pk_limit) break;   // pulled bins are last
         a.first = b.first;
         a.count = b.count;
         a.cpw = b.cpw;
@@ -1202,7 +1329,10 @@ static std::vector<Bin> split_bins(const std::vector<Bin> &in, const std::vector
             if (start >= b.first + b.count) break;
         }
     }
-    std::stable_sort(out.begin(), out.end(), [](const Bin &a, const Bin &b) { return a.cost > b.cost; });
+    std::stable_sort(out.begin(), out.end(), [](const Bin &a, const Bin &b) {
+        if (a.pk != b.pk) return a.pk < b.pk;   // pullable bins stay last
+        return a.cost > b.cost;
+    });
     return out;
 }
 
@@ -1255,57 +1385,110 @@ static void clear_graphs(ffsat_plan *pl)
 template <typename IO>
 static ffsat_status run_eval(ffsat_plan *pl, const IO *x, IO *F, IO *grad, IO *con_val, int32_t *n_sat,
                              uint32_t *unsat_bits, int32_t *U, bool do_value, float *x_step, float eta,
-                             hipStream_t s, const float *eta_dev = nullptr, const int32_t *skip = nullptr);
+                             hipStream_t s, const float *eta_dev = nullptr, const int32_t *skip = nullptr,
+                             float *x_next = nullptr);
 
-// With MODE_AUTO, times one full FP32 evaluation with the fused step (on the
-// tuner's scratch points, step size 0) under each launch structure and keeps
-// the fastest; the choice is cached with the shapes.
+// Switches the pull path to class c (PULL_OFF, PULL_LE7, PULL_LE3): builds
+// the problem's entry lists for c on first use and the plan's second point
+// buffer.  A class without pullable bins, or the grouped launch of every
+// bin (which holds the transform-free bins), turns it off; PULL_LE7 without
+// constraints of length 4..7 is PULL_LE3.  Changing the class drops the
+// cached graphs.
+static ffsat_status set_pull(ffsat_plan *pl, int c)
+{
+    if (c == PULL_LE7) {
+        bool mid = false;
+        for (const Bin &b : pl->bins[IO_F32]) mid = mid || b.pk == PULL_LE7;
+        if (!mid) c = PULL_LE3;
+    }
+    if (c != PULL_OFF) {
+        bool any = false;
+        for (const Bin &b : pl->bins[IO_F32]) any = any || b.pk >= c;
+        // k_pull's gathers are buffer loads with 31-bit offsets into x
+        const bool fits = (int64_t)pl->p->n * pl->B * 4 <= 0x7fffffffll;
+        if (!any || !fits || pl->mode == MODE_GROUP_ALL) c = PULL_OFF;
+    }
+    if (c != PULL_OFF) {
+        ffsat_status st = build_pull(pl->p, c);
+        if (st != FFSAT_OK) return st;
+        if (!pl->d_xalt) {
+            const size_t bytes = sizeof(float) * (size_t)pl->p->n * (size_t)pl->B;
+            HIPCHK(hipMalloc(&pl->d_xalt, bytes));
+            pl->device_bytes += (int64_t)bytes;
+        }
+    }
+    if (c != pl->pull) clear_graphs(pl);
+    pl->pull = c;
+    return FFSAT_OK;
+}
+
+// With MODE_AUTO (or an automatic pull choice), times one full FP32
+// evaluation with the fused step (on the tuner's scratch points, step size
+// 0, the stepped point written to the second buffer as in the step loops)
+// under each launch structure and pull class and keeps the fastest; the
+// choice is cached with the shapes.
 static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cache, hipStream_t s)
 {
-    if (!pl->mode_auto) return FFSAT_OK;
-    char kb[160];
-    snprintf(kb, sizeof kb, "gfx950|mode|B%d|n%d|m%d|nnz%lld|bins%zu", pl->B, pl->p->n, pl->p->m,
-             (long long)pl->p->nnz, pl->bins[IO_F32].size());
-    const std::string key = kb;
+    if (!pl->mode_auto && !pl->pull_auto) return FFSAT_OK;
+    char kb[200];
+    snprintf(kb, sizeof kb, "gfx950|mode|B%d|n%d|m%d|nnz%lld|bins%zu|%s%d", pl->B, pl->p->n, pl->p->m,
+             (long long)pl->p->nnz, pl->bins[IO_F32].size(), pl->mode_auto ? "a" : "f", pl->mode);
+    const std::string key = pl->pull_auto ? std::string(kb) + "|pull" : std::string(kb) + "|p" + std::to_string(pl->pull);
     auto hit = cache.find(key);
-    int best_mode = MODE_GROUP_DFT;
-    if (hit != cache.end() && hit->second.cpw >= MODE_PER_BIN && hit->second.cpw <= MODE_GROUP_DFT) {
+    int best_mode = pl->mode, best_pull = pl->pull;
+    if (hit != cache.end() && hit->second.cpw >= MODE_PER_BIN && hit->second.cpw <= MODE_GROUP_DFT &&
+        hit->second.wpb >= PULL_OFF && hit->second.wpb <= PULL_LE3) {
         best_mode = hit->second.cpw;
+        best_pull = hit->second.wpb;
     } else {
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         float best = 1e30f;
-        for (int m : {MODE_GROUP_DFT, MODE_GROUP_ALL, MODE_PER_BIN}) {
-            pl->mode = m;
-            pl->grouped = m != MODE_PER_BIN;
-            ffsat_status st = build_groups(pl);
-            if (st != FFSAT_OK) return st;
-            if ((st = run_eval<float>(pl, pl->d_scratch_x, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true,
-                                      pl->d_scratch_x, 0.f, s)) != FFSAT_OK)
-                return st;
-            HIPCHK(hipEventRecord(e0, s));
-            const int reps = 5;
-            for (int r = 0; r < reps; ++r)
+        std::vector<int> modes = pl->mode_auto ? std::vector<int>{MODE_GROUP_DFT, MODE_GROUP_ALL, MODE_PER_BIN}
+                                               : std::vector<int>{pl->mode};
+        std::vector<int> pulls = pl->pull_auto ? std::vector<int>{PULL_OFF, PULL_LE3, PULL_LE7}
+                                               : std::vector<int>{pl->pull};
+        std::vector<std::pair<int, int>> tried;
+        for (int m : modes) {
+            for (int c : pulls) {
+                pl->mode = m;
+                pl->grouped = m != MODE_PER_BIN;
+                ffsat_status st = set_pull(pl, c);
+                if (st != FFSAT_OK) return st;
+                const std::pair<int, int> cand{m, pl->pull};
+                if (std::find(tried.begin(), tried.end(), cand) != tried.end()) continue;
+                tried.push_back(cand);
+                if ((st = build_groups(pl)) != FFSAT_OK) return st;
+                float *out = pl->pull ? pl->d_xalt : nullptr;
                 if ((st = run_eval<float>(pl, pl->d_scratch_x, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                          true, pl->d_scratch_x, 0.f, s)) != FFSAT_OK)
+                                          true, pl->d_scratch_x, 0.f, s, nullptr, nullptr, out)) != FFSAT_OK)
                     return st;
-            HIPCHK(hipEventRecord(e1, s));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best * 0.97f) {
-                best = ms;
-                best_mode = m;
+                HIPCHK(hipEventRecord(e0, s));
+                const int reps = 5;
+                for (int r = 0; r < reps; ++r)
+                    if ((st = run_eval<float>(pl, pl->d_scratch_x, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                              nullptr, true, pl->d_scratch_x, 0.f, s, nullptr, nullptr, out)) !=
+                        FFSAT_OK)
+                        return st;
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best * 0.97f) {
+                    best = ms;
+                    best_mode = m;
+                    best_pull = pl->pull;
+                }
             }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        cache[key] = Shape{best_mode, 1, 1};   // stored in the cpw field
+        cache[key] = Shape{best_mode, best_pull, 1};   // mode in the cpw field, pull class in wpb
     }
     pl->mode = best_mode;
     pl->grouped = best_mode != MODE_PER_BIN;
-    return FFSAT_OK;
+    return set_pull(pl, best_pull);
 }
 
 extern "C" ffsat_status ffsat_plan_tune(ffsat_plan *pl, void *stream)
@@ -1420,6 +1603,16 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
     pl->mode_auto = req == MODE_AUTO;
     pl->mode = pl->mode_auto ? MODE_GROUP_DFT : req;   // the tuner may change an automatic choice
     pl->grouped = pl->mode != MODE_PER_BIN;
+    const int preq = opts ? opts->reserved[2] : 0;
+    const int vc = opts ? opts->reserved[3] : 0;
+    if (preq < 0 || preq > 3 || vc < 0 || vc > PULL_VC_MAX ||
+        (opts && (opts->reserved[4] || opts->reserved[5] || opts->reserved[6] || opts->reserved[7]))) {
+        delete pl;
+        return fail(FFSAT_E_INVALID_ARG, "reserved[2] (pull) must be in 0..3, reserved[3] (variables per wave) in "
+                                         "0..8, reserved[4..7] must be 0");
+    }
+    pl->pull_auto = preq == 0;
+    pl->pull_vc = vc > 0 ? vc : 8;
     default_shapes(pl);
     pl->use_graphs = opts ? opts->use_graphs != 0 : true;
     if (opts && opts->tune_cache) pl->tune_cache = opts->tune_cache;
@@ -1442,6 +1635,7 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
             if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
         if (e != hipSuccess) st = fail(FFSAT_E_HIP, "side streams: %s", hipGetErrorString(e));
     }
+    if (st == FFSAT_OK && !pl->pull_auto) st = set_pull(pl, preq == 1 ? PULL_OFF : (preq == 2 ? PULL_LE7 : PULL_LE3));
     if (st == FFSAT_OK) st = build_groups(pl);
     if (st == FFSAT_OK && opts && opts->autotune) {
         st = ffsat_plan_tune(pl, nullptr);
@@ -1506,6 +1700,7 @@ extern "C" ffsat_status ffsat_plan_destroy(ffsat_plan *pl)
     for (hipEvent_t e : pl->prof_pool) (void)hipEventDestroy(e);
     clear_graphs(pl);
     (void)hipFree(pl->d_hyper);
+    (void)hipFree(pl->d_xalt);
     (void)hipFree(pl->d_gent);
     (void)hipFree(pl->d_gblk);
     for (int io = 0; io < 2; ++io) {
@@ -1548,7 +1743,9 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
       << mode_names[pl->mode] << "\"" << ", \"mode_auto\": " << (pl->mode_auto ? "true" : "false")
       << ", \"grouped\": " << (pl->grouped && pl->gblocks > 0 ? "true" : "false") << ", \"group_blocks\": " << pl->gblocks
       << ", \"solo_bins\": " << pl->gsolo.size() << ", \"graphs_cached\": " << pl->graphs.size()
-      << ", \"graph_captures\": " << pl->captures << ", \"bins\": {";
+      << ", \"graph_captures\": " << pl->captures << ", \"pull\": " << PULL_K[pl->pull]
+      << ", \"pull_auto\": " << (pl->pull_auto ? "true" : "false") << ", \"pull_vc\": " << pl->pull_vc
+      << ", \"pull_entries\": " << (pl->pull ? pl->p->lay[IO_F32].pull[pl->pull].n_ent : 0) << ", \"bins\": {";
     for (int io = 0; io < 2; ++io) {
         o << (io ? ", " : "") << "\"" << (io ? "f64" : "f32") << "\": [";
         for (size_t i = 0; i < pl->bins[io].size(); ++i) {
@@ -1559,6 +1756,7 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
               << ", \"lits\": " << b.lits << ", \"cost\": " << b.cost << ", \"flops_per_restart\": " << b.flops
               << ", \"bytes_per_restart\": " << b.bytes << ", \"positions_per_restart\": " << b.exec_pos
               << ", \"k2_per_restart\": " << b.k2
+              << ", \"pull_class\": " << b.pk << ", \"pulled\": " << (io == IO_F32 && pl->pull && b.pk >= pl->pull ? "true" : "false")
               << ", \"cpw\": " << b.cpw
               << ", \"wpb\": " << b.wpb << ", \"fg\": " << b.fg << ", \"in_group\": "
               << ((io == IO_F32 && pl->grouped && pl->gblocks > 0 &&
@@ -1594,27 +1792,67 @@ static ffsat_status check_finite(ffsat_plan *pl, const IO *x, hipStream_t s)
     return FFSAT_OK;
 }
 
-// One evaluation pass: optional value/gradient/objective outputs, optional
-// exact check of the same point, optional fused projected step.
-template <typename IO>
-static ffsat_status run_eval(ffsat_plan *pl, const IO *x, IO *F, IO *grad, IO *con_val, int32_t *n_sat,
-                             uint32_t *unsat_bits, int32_t *U, bool do_value, float *x_step, float eta,
-                             hipStream_t s, const float *eta_dev, const int32_t *skip)
+// The pull path serves an FP32 evaluation that produces a gradient or a step
+// and no per-constraint values.
+static bool pull_on(const ffsat_plan *pl, int io, bool do_value, const void *con_val, bool grad_or_step)
 {
-    const int io = sizeof(IO) == 4 ? IO_F32 : IO_F64;
+    return io == IO_F32 && pl->pull > 0 && do_value && con_val == nullptr && grad_or_step;
+}
+
+// Objective / count rows an evaluation writes: the launched bins' rows (the
+// first rows), then with the pull path one row per variable chunk.
+static int eval_rows(const ffsat_plan *pl, int io, int pull)
+{
+    int rows = 0;
+    for (const Bin &b : pl->bins[io])
+        if (!pull || b.pk < pull) rows += (b.count + b.cpw - 1) / b.cpw;
+    if (pull) rows += (pl->p->n + pl->pull_vc - 1) / pl->pull_vc;
+    return rows;
+}
+
+// k_pull: the gradient (grad) or the projected step (x_out != x), the
+// objective and check rows of the pulled constraints, and the gradient
+// share of every other constraint from its slots.
+static hipError_t enqueue_pull(ffsat_plan *pl, const float *x, float *grad, float *x_out, float eta,
+                               const float *eta_dev, uint32_t *unsat_bits, int32_t *U, bool want_check,
+                               const int32_t *skip, hipStream_t s)
+{
     const ffsat_problem *p = pl->p;
-    const bool want_check = n_sat || unsat_bits || U;
-    if (!do_value && !want_check) return FFSAT_OK;
-    if (U) HIPCHK(launch_fill_i32(U, p->m, 0, s));
-    if (unsat_bits) HIPCHK(launch_fill_i32((int32_t *)unsat_bits, (int64_t)((p->m + 31) / 32) * pl->B, 0, s));
-    const bool grad_slots = do_value && (grad != nullptr || x_step != nullptr);
-    EvalArgs<IO> a = base_args<IO>(pl, io, x, do_value ? con_val : nullptr, grad_slots);
-    a.do_value = do_value ? 1 : 0;
-    a.want_check = want_check ? 1 : 0;
+    const PullLayout &P = p->lay[IO_F32].pull[pl->pull];
+    if (!P.built) return hipErrorNotReady;
+    PullArgs a{};
+    a.x = x;
+    a.x_out = x_out;
+    a.grad = grad;
+    a.slot = (const float *)pl->d_slot[IO_F32];
+    a.vptr = P.d_vptr;
+    a.vslot = P.d_vslot;
+    a.pptr = P.d_pptr;
+    a.pent = P.d_pent;
+    a.w = p->d_w;
+    a.fpart = (float *)pl->d_fpart[IO_F32];
+    a.cpart = pl->d_cpart;
     a.unsat_bits = unsat_bits;
     a.U = U;
+    a.eta_dev = eta_dev;
     a.skip = skip;
-    HIPCHK(enqueue_bins<IO>(pl, io, a, s));
+    a.eta = eta;
+    a.n = p->n;
+    a.B = pl->B;
+    a.vc = pl->pull_vc;
+    a.row0 = eval_rows(pl, IO_F32, pl->pull) - (p->n + pl->pull_vc - 1) / pl->pull_vc;
+    a.wm = (p->m + 31) / 32;
+    a.want_check = want_check ? 1 : 0;
+    a.rk = P.d_rk;
+    a.x_bytes = (int64_t)p->n * pl->B * (int64_t)sizeof(float);
+    return launch_pull(PULL_E[pl->pull], a, s);
+}
+
+template <typename IO>
+static ReduceArgs<IO> reduce_args(ffsat_plan *pl, int io, IO *grad, float *x_step, float eta, const float *eta_dev,
+                                  const int32_t *skip, IO *F, int32_t *n_sat, int pull)
+{
+    const ffsat_problem *p = pl->p;
     const Layout &Ly = p->lay[io];
     ReduceArgs<IO> r{};
     r.n = p->n;
@@ -1623,23 +1861,63 @@ static ffsat_status run_eval(ffsat_plan *pl, const IO *x, IO *F, IO *grad, IO *c
     r.vptr = Ly.d_vptr;
     r.vslot = Ly.d_vslot;
     r.slot = (const IO *)pl->d_slot[io];
-    r.grad = do_value ? grad : nullptr;
-    r.x_step = do_value ? x_step : nullptr;
+    r.grad = pull ? nullptr : grad;
+    r.x_step = pull ? nullptr : x_step;
     r.eta = eta;
     r.eta_dev = eta_dev;
     r.skip = skip;
     r.fpart = (const IO *)pl->d_fpart[io];
     r.cpart = pl->d_cpart;
-    r.rows = pl->fpart_rows[io];
+    r.rows = eval_rows(pl, io, pull);
     r.ftmp = (IO *)pl->d_ftmp[io];
     r.ctmp = pl->d_ctmp;
-    r.F = do_value ? F : nullptr;
+    r.F = F;
     r.n_sat = n_sat;
+    return r;
+}
+
+// One evaluation pass: optional value/gradient/objective outputs, optional
+// exact check of the same point, optional fused projected step (in place
+// into x_step; with the pull path, into x_next when given, else through
+// the plan's second point buffer and a copy back).
+template <typename IO>
+static ffsat_status run_eval(ffsat_plan *pl, const IO *x, IO *F, IO *grad, IO *con_val, int32_t *n_sat,
+                             uint32_t *unsat_bits, int32_t *U, bool do_value, float *x_step, float eta,
+                             hipStream_t s, const float *eta_dev, const int32_t *skip, float *x_next)
+{
+    const int io = sizeof(IO) == 4 ? IO_F32 : IO_F64;
+    const ffsat_problem *p = pl->p;
+    const bool want_check = n_sat || unsat_bits || U;
+    if (!do_value && !want_check) return FFSAT_OK;
+    if (U) HIPCHK(launch_fill_i32(U, p->m, 0, s));
+    if (unsat_bits) HIPCHK(launch_fill_i32((int32_t *)unsat_bits, (int64_t)((p->m + 31) / 32) * pl->B, 0, s));
+    const bool grad_slots = do_value && (grad != nullptr || x_step != nullptr);
+    const int pull = pull_on(pl, io, do_value, con_val, grad_slots) ? pl->pull : 0;
+    EvalArgs<IO> a = base_args<IO>(pl, io, x, do_value ? con_val : nullptr, grad_slots);
+    a.do_value = do_value ? 1 : 0;
+    a.want_check = want_check ? 1 : 0;
+    a.unsat_bits = unsat_bits;
+    a.U = U;
+    a.skip = skip;
+    HIPCHK(enqueue_bins<IO>(pl, io, a, s, pull ? pull : 3));
+    ReduceArgs<IO> r = reduce_args<IO>(pl, io, do_value ? grad : nullptr, do_value ? x_step : nullptr, eta, eta_dev,
+                                       skip, do_value ? F : nullptr, n_sat, pull);
     ProfRec rec;
     prof_begin(pl, s, prof_active(pl, s), rec, io, -1);
-    hipError_t e;
-    if constexpr (sizeof(IO) == 4) e = launch_reduce_f32(r, s);
-    else e = launch_reduce_f64(r, s);
+    hipError_t e = hipSuccess;
+    if constexpr (sizeof(IO) == 4) {
+        if (pull) {
+            float *out = nullptr;
+            if (x_step) out = x_next ? x_next : pl->d_xalt;
+            e = enqueue_pull(pl, (const float *)x, x_step ? nullptr : (float *)grad, out, eta, eta_dev, unsat_bits, U,
+                             want_check, skip, s);
+            if (e == hipSuccess && x_step && !x_next)
+                e = launch_copy_f32(x_step, pl->d_xalt, (int64_t)p->n * pl->B, s);
+        }
+        if (e == hipSuccess) e = launch_reduce_f32(r, s);
+    } else {
+        e = launch_reduce_f64(r, s);
+    }
     prof_end(pl, s, rec);
     HIPCHK(e);
     return FFSAT_OK;
@@ -1707,6 +1985,43 @@ extern "C" ffsat_status ffsat_step_f64(ffsat_plan *pl, double *x, const double *
     return FFSAT_OK;
 }
 
+// Before a capture ends, every side stream of the plan that joined it must
+// have been joined back into the capturing stream: each node at a side
+// stream's tail must either be a dependency of the capturing stream's next
+// node or have a dependent node of its own.  An unjoined stream is reported
+// here, and the capture abandoned, instead of being left to the runtime.
+static hipError_t check_joined(const ffsat_plan *pl, hipStream_t origin, int *unjoined)
+{
+    *unjoined = -1;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    unsigned long long id = 0;
+    const hipGraphNode_t *deps = nullptr;
+    size_t nd = 0;
+    hipError_t e = hipStreamGetCaptureInfo_v2(origin, &st, &id, nullptr, &deps, &nd);
+    if (e != hipSuccess || st != hipStreamCaptureStatusActive) return e;
+    const std::vector<hipGraphNode_t> od(deps, deps + nd);
+    const hipStream_t sides[] = {pl->side[0], pl->side[1], pl->side[2], pl->iter_side};
+    for (int i = 0; i < 4; ++i) {
+        if (!sides[i]) continue;
+        hipStreamCaptureStatus s2 = hipStreamCaptureStatusNone;
+        unsigned long long id2 = 0;
+        const hipGraphNode_t *d2 = nullptr;
+        size_t n2 = 0;
+        if ((e = hipStreamGetCaptureInfo_v2(sides[i], &s2, &id2, nullptr, &d2, &n2)) != hipSuccess) return e;
+        if (s2 != hipStreamCaptureStatusActive || id2 != id) continue;
+        for (size_t j = 0; j < n2; ++j) {
+            if (std::find(od.begin(), od.end(), d2[j]) != od.end()) continue;
+            size_t ndep = 0;
+            if ((e = hipGraphNodeGetDependentNodes(d2[j], nullptr, &ndep)) != hipSuccess) return e;
+            if (ndep == 0) {
+                *unjoined = i;
+                return hipSuccess;
+            }
+        }
+    }
+    return hipSuccess;
+}
+
 // The executable graph of a launch sequence, captured once per key on the
 // plan's capture stream (side-stream bins become parallel branches) and kept
 // (at most 16 per plan; beyond that all are dropped, each after its latest
@@ -1719,11 +2034,14 @@ static ffsat_status cached_graph(ffsat_plan *pl, const GraphKey &key, Body body,
     if (it == pl->graphs.end()) {
         if (!pl->cap) HIPCHK(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
-        const hipError_t e = body(pl->cap);
+        hipError_t e = body(pl->cap);
+        int unjoined = -1;
+        if (e == hipSuccess) e = check_joined(pl, pl->cap, &unjoined);
         hipGraph_t g = nullptr;
         const hipError_t e2 = hipStreamEndCapture(pl->cap, &g);
-        if (e != hipSuccess || e2 != hipSuccess) {
+        if (e != hipSuccess || e2 != hipSuccess || unjoined >= 0) {
             if (g) (void)hipGraphDestroy(g);
+            if (unjoined >= 0) return fail(FFSAT_E_HIP, "graph capture: side stream %d was not joined back", unjoined);
             return fail(FFSAT_E_HIP, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
         }
         GraphEntry ent;
@@ -1750,11 +2068,21 @@ static ffsat_status launch_graph(GraphEntry *g, hipStream_t s)
     return FFSAT_OK;
 }
 
-static hipError_t enqueue_step_iter(ffsat_plan *pl, float *x, float *F, hipStream_t s)
+// T projected steps.  With the pull path the steps alternate between x and
+// the plan's second point buffer (k_pull never writes the point it reads);
+// an odd count ends with a copy back into x.
+static hipError_t enqueue_steps(ffsat_plan *pl, float *x, int T, float *F_last, hipStream_t s)
 {
-    const ffsat_status st =
-        run_eval<float>(pl, x, F, nullptr, nullptr, nullptr, nullptr, nullptr, true, x, 0.f, s, pl->d_hyper);
-    return st == FFSAT_OK ? hipSuccess : hipErrorUnknown;
+    const bool pp = pl->pull > 0;
+    float *cur = x, *nxt = pl->d_xalt;
+    for (int t = 0; t < T; ++t) {
+        if (run_eval<float>(pl, cur, t == T - 1 ? F_last : nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true,
+                            cur, 0.f, s, pl->d_hyper, nullptr, pp ? nxt : nullptr) != FFSAT_OK)
+            return hipErrorUnknown;
+        if (pp) std::swap(cur, nxt);
+    }
+    if (cur != x) return launch_copy_f32(x, cur, (int64_t)pl->p->n * pl->B, s);
+    return hipSuccess;
 }
 
 extern "C" ffsat_status ffsat_run_steps(ffsat_plan *pl, float *x, int32_t T, float eta, float *F_last, void *stream)
@@ -1769,7 +2097,7 @@ extern "C" ffsat_status ffsat_run_steps(ffsat_plan *pl, float *x, int32_t T, flo
     // the step size goes to device memory ahead of the (captured) steps
     HIPCHK(launch_set_f32x2(pl->d_hyper, eta, 0.f, s));
     if (!pl->use_graphs) {
-        for (int t = 0; t < T; ++t) HIPCHK(enqueue_step_iter(pl, x, t == T - 1 ? F_last : nullptr, s));
+        HIPCHK(enqueue_steps(pl, x, T, F_last, s));
         return FFSAT_OK;
     }
     GraphKey key{};
@@ -1778,82 +2106,81 @@ extern "C" ffsat_status ffsat_run_steps(ffsat_plan *pl, float *x, int32_t T, flo
     key.T = T;
     key.F = F_last;
     GraphEntry *g = nullptr;
-    if ((st = cached_graph(pl, key, [&](hipStream_t cs) {
-             hipError_t e = hipSuccess;
-             for (int t = 0; t < T && e == hipSuccess; ++t)
-                 e = enqueue_step_iter(pl, x, t == T - 1 ? F_last : nullptr, cs);
-             return e;
-         }, &g)) != FFSAT_OK)
+    if ((st = cached_graph(pl, key, [&](hipStream_t cs) { return enqueue_steps(pl, x, T, F_last, cs); }, &g)) !=
+        FFSAT_OK)
         return st;
     return launch_graph(g, s);
 }
 
 // T fused iterations: objective, exact check and projected step of x_t, then
-// the adaptive weights from that iteration's violation counts (alpha > 0)
-static hipError_t enqueue_iter(ffsat_plan *pl, float *x, bool erwa, float *F, int32_t *n_sat, int32_t *U,
-                               hipStream_t s)
+// the adaptive weights from that iteration's violation counts (alpha > 0).
+// With the pull path the iterates alternate between x and the plan's second
+// point buffer, and an odd count ends with a copy back into x.
+static hipError_t enqueue_iters(ffsat_plan *pl, float *x, int T, bool erwa, float *F, int32_t *n_sat, int32_t *U,
+                                hipStream_t s)
 {
-    if (run_eval<float>(pl, x, F, nullptr, nullptr, n_sat, nullptr, U, true, x, 0.f, s, pl->d_hyper) != FFSAT_OK)
-        return hipErrorUnknown;
-    if (erwa) return launch_erwa(pl->p->m, U, pl->p->d_w, 0.f, pl->d_hyper + 1, pl->d_umax, s);
+    const bool pp = pl->pull > 0;
+    float *cur = x, *nxt = pl->d_xalt;
+    for (int t = 0; t < T; ++t) {
+        if (run_eval<float>(pl, cur, F, nullptr, nullptr, n_sat, nullptr, U, true, cur, 0.f, s, pl->d_hyper, nullptr,
+                            pp ? nxt : nullptr) != FFSAT_OK)
+            return hipErrorUnknown;
+        if (erwa) {
+            const hipError_t e = launch_erwa(pl->p->m, U, pl->p->d_w, 0.f, pl->d_hyper + 1, pl->d_umax, s);
+            if (e != hipSuccess) return e;
+        }
+        if (pp) std::swap(cur, nxt);
+    }
+    if (cur != x) return launch_copy_f32(x, cur, (int64_t)pl->p->n * pl->B, s);
     return hipSuccess;
 }
 
 // The same T iterations with the work that only needs iteration t's counts
-// or level-1 sums moved to a side stream: after evaluation t, the adaptive
-// weights and the reset of U for t+1 run beside the gradient reduction; after
-// reduction t, the level-2 sums (F, n_sat of x_t) run beside evaluation t+1.
-// Evaluation t+1 waits for the weights and the reset; reduction t+1 (which
-// rewrites the level-1 sums) waits for the level-2 sums of t; the caller's
-// stream waits for the side stream at the end.
+// or level-1 sums moved to a side stream: after the counts of iteration t
+// are complete (the evaluation, and with the pull path k_pull, which checks
+// the pulled constraints), the adaptive weights and the reset of U for t+1
+// run beside the rest of the reduction; after reduction t, the level-2 sums
+// (F, n_sat of x_t) run beside evaluation t+1.  Evaluation t+1 waits for the
+// weights and the reset; reduction t+1 (which rewrites the level-1 sums)
+// waits for the level-2 sums of t; the caller's stream waits for the side
+// stream at the end.
 static hipError_t enqueue_iters_overlapped(ffsat_plan *pl, float *x, int T, bool erwa, float *F,
                                            int32_t *n_sat, int32_t *U, hipStream_t s)
 {
     const ffsat_problem *p = pl->p;
     hipStream_t q = pl->iter_side;
+    const int pull = pl->pull;
+    const bool want_check = n_sat || U;
     hipError_t e;
 #define ITER_CHK(call) \
     if ((e = (call)) != hipSuccess) return e
-    ReduceArgs<float> r{};
-    r.n = p->n;
-    r.B = pl->B;
-    r.m = p->m;
-    r.vptr = p->lay[IO_F32].d_vptr;
-    r.vslot = p->lay[IO_F32].d_vslot;
-    r.slot = (const float *)pl->d_slot[IO_F32];
-    r.grad = nullptr;
-    r.x_step = x;
-    r.eta = 0.f;
-    r.eta_dev = pl->d_hyper;
-    r.fpart = (const float *)pl->d_fpart[IO_F32];
-    r.cpart = pl->d_cpart;
-    r.rows = pl->fpart_rows[IO_F32];
-    r.ftmp = (float *)pl->d_ftmp[IO_F32];
-    r.ctmp = pl->d_ctmp;
-    r.F = F;
-    r.n_sat = n_sat;
+    float *cur = x, *nxt = pl->d_xalt;
     if (U) ITER_CHK(launch_fill_i32(U, p->m, 0, s));
     for (int t = 0; t < T; ++t) {
-        EvalArgs<float> a = base_args<float>(pl, IO_F32, x, nullptr, true);
+        EvalArgs<float> a = base_args<float>(pl, IO_F32, cur, nullptr, true);
         a.do_value = 1;
-        a.want_check = (n_sat || U) ? 1 : 0;
+        a.want_check = want_check ? 1 : 0;
         a.unsat_bits = nullptr;
         a.U = U;
         if (t > 0) ITER_CHK(hipStreamWaitEvent(s, pl->ev_aux, 0));   // weights and reset of t-1
-        ITER_CHK(enqueue_bins<float>(pl, IO_F32, a, s));
+        ITER_CHK(enqueue_bins<float>(pl, IO_F32, a, s, pull ? pull : 3));
+        if (pull) ITER_CHK(enqueue_pull(pl, cur, nullptr, nxt, 0.f, pl->d_hyper, nullptr, U, want_check, nullptr, s));
         ITER_CHK(hipEventRecord(pl->ev_eval, s));
         ITER_CHK(hipStreamWaitEvent(q, pl->ev_eval, 0));
         if (erwa) ITER_CHK(launch_erwa(p->m, U, p->d_w, 0.f, pl->d_hyper + 1, pl->d_umax, q));
         if (U && t < T - 1) ITER_CHK(launch_fill_i32(U, p->m, 0, q));
         ITER_CHK(hipEventRecord(pl->ev_aux, q));
         if (t > 0) ITER_CHK(hipStreamWaitEvent(s, pl->ev_sum, 0));   // level-2 sums of t-1 read the level-1 rows
+        const ReduceArgs<float> r = reduce_args<float>(pl, IO_F32, nullptr, cur, 0.f, pl->d_hyper, nullptr, F, n_sat, pull);
         ITER_CHK(launch_reduce_part_f32(r, 1, s));
         ITER_CHK(hipEventRecord(pl->ev_red, s));
         ITER_CHK(hipStreamWaitEvent(q, pl->ev_red, 0));
         ITER_CHK(launch_reduce_part_f32(r, 2, q));
         ITER_CHK(hipEventRecord(pl->ev_sum, q));
+        if (pull) std::swap(cur, nxt);
     }
     ITER_CHK(hipStreamWaitEvent(s, pl->ev_sum, 0));
+    if (cur != x) ITER_CHK(launch_copy_f32(x, cur, (int64_t)p->n * pl->B, s));
 #undef ITER_CHK
     return hipSuccess;
 }
@@ -1875,9 +2202,7 @@ extern "C" ffsat_status ffsat_run_iters(ffsat_plan *pl, float *x, int32_t T, flo
     HIPCHK(launch_set_f32x2(pl->d_hyper, eta, alpha, s));
     auto body = [&](hipStream_t cs) {
         if (pl->iter_side) return enqueue_iters_overlapped(pl, x, T, erwa, F, n_sat, U, cs);
-        hipError_t e = hipSuccess;
-        for (int t = 0; t < T && e == hipSuccess; ++t) e = enqueue_iter(pl, x, erwa, F, n_sat, U, cs);
-        return e;
+        return enqueue_iters(pl, x, T, erwa, F, n_sat, U, cs);
     };
     if (!pl->use_graphs) {
         HIPCHK(body(s));

@@ -66,6 +66,29 @@ struct Bin {
     int cpw = 1, wpb = 4;       // tile shape: constraints per wave, waves per block
     int fg = 1;                 // root-of-unity bins: waves splitting one unit's frequencies
     bool uc = false;            // root-of-unity bin in the unit-circle form (ablation)
+    int pk = 0;                 // pull class: 2 = transform-free, length <= 3; 1 = transform-free,
+                                // length 4..7; 0 = other (bins are ordered by pk, then cost)
+};
+
+// Pull classes: the gradient of the transform-free constraints of a class
+// >= the plan's pull threshold is gathered per variable (k_pull) instead of
+// written to slots and reduced.  PULL_K[c] is the longest constraint of
+// class c, PULL_E[c] the entry width in int32: {constraint, meta, the other
+// PULL_K - 1 literals}.
+enum { PULL_OFF = 0, PULL_LE7 = 1, PULL_LE3 = 2 };
+constexpr int PULL_K[3] = {0, 7, 3};
+constexpr int PULL_E[3] = {0, 8, 4};
+constexpr int PULL_VC_MAX = 8;   // variables per wave of k_pull (its LDS holds their sums and points)
+
+// Pulled occurrences of the constraints of pull class >= c, per variable.
+struct PullLayout {
+    bool built = false;
+    int64_t n_ent = 0;           // pulled (literal occurrence) entries
+    int32_t *d_pptr = nullptr;   // [n+1] variable -> first entry
+    int32_t *d_pent = nullptr;   // [n_ent][PULL_E[c]]
+    int32_t *d_vptr = nullptr;   // [n+1] variable-major transpose of the remaining slots
+    int32_t *d_vslot = nullptr;  // ascending slot order per variable
+    float *d_rk = nullptr;       // [RK_TABLE] coefficients of the transform-free kinds
 };
 
 struct ProfRec {
@@ -89,7 +112,18 @@ struct Layout {
     FreqF64 *d_f64 = nullptr;
     int n_types = 0;
     int64_t n_freqs = 0;
+    // host copies of the binned descriptors and literals (FP32 layout: the
+    // pulled-occurrence lists are built from them on first use)
+    std::vector<ConDesc> h_con;
+    std::vector<int32_t> h_lit;
+    std::vector<int8_t> h_rk;    // [m] binned order: transform-free kind (RKIND_*) or -1
+    PullLayout pull[3];          // by pull threshold class (index 1, 2)
 };
+
+// Transform-free kinds of the pull path: OR, AND, odd / even XOR, and the
+// constants -1 / +1 (thresholds outside [1, k]).
+enum { RKIND_OR = 0, RKIND_AND = 1, RKIND_XOR_ODD = 2, RKIND_XOR_EVEN = 3, RKIND_TRUE = 4, RKIND_FALSE = 5,
+       RKIND_N = 6 };
 
 }  // namespace ffsat
 
@@ -220,6 +254,12 @@ struct ffsat_plan {
     std::string tune_cache;
     std::map<ffsat::GraphKey, ffsat::GraphEntry> graphs;
     float *d_hyper = nullptr;        // [2] step size and weight-update rate read by captured graphs
+    // pulled gradient of the short transform-free constraints (PULL_*;
+    // chosen by the tuner unless fixed by the options)
+    int pull = 0;
+    bool pull_auto = false;
+    int pull_vc = 8;                 // variables per wave of k_pull
+    float *d_xalt = nullptr;         // [n][B] second point buffer of in-place pulled steps
     int64_t captures = 0;            // graphs captured over the plan's life
     int64_t device_bytes = 0;
     bool profiling = false;
@@ -260,6 +300,38 @@ struct ReduceArgs {
     const int32_t *skip;   // if set and *skip == 0, the reduction does nothing
 };
 hipError_t launch_reduce_f32(const ReduceArgs<float> &r, hipStream_t s);
+
+// Pulled gradient (k_pull): for every variable of a chunk of vc variables
+// and 64 restarts, the remaining constraints' slots (ascending slot order)
+// plus the pulled occurrences' terms (entry order), summed in FP64; then
+// either the gradient or the projected step into x_out (never x).  The
+// objective term and the exact check of every pulled constraint are taken
+// at the entry of its first literal; one objective / count row per chunk.
+struct PullArgs {
+    const float *x;
+    float *x_out;             // projected step (x_out != x), or null
+    float *grad;              // gradient, or null (exactly one of x_out, grad)
+    const float *slot;
+    const int32_t *vptr, *vslot;
+    const int32_t *pptr, *pent;
+    const float *w;
+    float *fpart;
+    int32_t *cpart;
+    uint32_t *unsat_bits;
+    int32_t *U;
+    const float *eta_dev;
+    const int32_t *skip;
+    float eta;
+    // per transform-free kind r: factor alpha + beta l, value coefficient c0,
+    // gradient coefficient c1 and constant at rk[r], rk[8 + r], rk[16 + r],
+    // rk[24 + r], rk[32 + r]
+    const float *rk;
+    int64_t x_bytes;               // size of x (buffer-load bound, < 2^31)
+    int n, B, vc, row0, wm, want_check;
+};
+constexpr int RK_TABLE = 40;
+hipError_t launch_pull(int E, const PullArgs &a, hipStream_t s);
+hipError_t launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t launch_reduce_f64(const ReduceArgs<double> &r, hipStream_t s);
 // parts: 1 = gradient / step and level 1 of the sums, 2 = level 2, 3 = both
 hipError_t launch_reduce_part_f32(const ReduceArgs<float> &r, int parts, hipStream_t s);

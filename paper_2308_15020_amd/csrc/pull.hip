@@ -1,0 +1,257 @@
+// Gradient of the short transform-free constraints by gathering instead of
+// scattering, fused with the reduction of every other constraint's slots
+// and the projected step.
+//
+// For a variable v that sits at position i of an OR / AND / XOR constraint
+// c, the term of dF/dx_v is w_c s_i c1 prod_{j != i} (alpha + beta l_j)
+// (the closed forms of App. B differentiated as in Eq. chain; s_i = -1 for
+// a negated literal).  The slot path computes it constraint by constraint,
+// writes it to a [nnz][B] slot buffer and reads it back per variable: two
+// passes over 4 bytes per (literal, restart) through HBM.  Here a wave owns
+// a chunk of variables and 64 restarts and, for each variable, walks a list
+// of entries {constraint, meta, the other literals} in a fixed order,
+// gathers the other literals' points and adds the term in FP64 after the
+// variable's remaining slots (longer constraints).  The objective term
+// w_c WE_c and the exact check of c (Alg. 1: x < 0 is True) are taken once,
+// at the entry of its first literal.
+//
+// Meta word: bits 0-2 transform-free kind, 3-5 k - 1, 6-9 check threshold
+// + 2 (>= 0: at least that many true literals; -1 / -2: even / odd
+// count), bit 10 this literal negated, bit 11 first literal of c.
+#include "internal.h"
+
+namespace ffsat {
+
+// Mapping: a wave owns a chunk of at most PULL_VC_MAX variables and RPL
+// blocks of 64 restarts (a lane holds restarts b, b + 64, ..): the decoding
+// of an entry (readlane of its fields, kind coefficients, weight) is paid
+// once for 64 * RPL restarts.  The chunk's list bounds are read with one
+// lane-parallel load; per variable, the other constraints' slots and then
+// the pulled entries are read in batches (one lane-parallel load of slot
+// indices or entry words, broadcast with readlane), all gathers of a batch
+// are issued before any term is added, and the terms are added in list
+// order.  Batches past a list's end read null entries (kind 7: every
+// coefficient zero) so that no term needs a branch.  Gathers are buffer
+// loads: the variable's row offset is scalar, the restart offset per lane.
+constexpr int RK_NULL = 7;
+constexpr int BUF_DW3 = 0x00020000;   // gfx9 buffer resource word 3 (raw 32-bit loads)
+
+__device__ __forceinline__ int lane_bcast(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+// one float of a buffer: lane offset (bytes) plus scalar offset (bytes)
+__device__ __forceinline__ float ldf(__amdgpu_buffer_rsrc_t r, int voff, unsigned soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, (int)soff, 0));
+}
+
+// Read-only arrays are separate __restrict__ arguments, so that the
+// compiler reads the uniform ones (kind table, weights) through the scalar
+// cache.
+template <int E, int RPL, bool STEP>
+__global__ __launch_bounds__(256) void k_pull(PullArgs a, const float *__restrict__ rkt, const float *__restrict__ wts,
+                                              const int32_t *__restrict__ pent, const int32_t *__restrict__ pptr,
+                                              const int32_t *__restrict__ vslot, const int32_t *__restrict__ vptr)
+{
+    constexpr int NO = E - 2;                              // other literals per entry
+    constexpr int NB = (64 / E) < (64 / (NO * RPL)) ? (64 / E) : (64 / (NO * RPL));   // entries per batch
+    constexpr int NS = 16 / RPL;                           // slots per batch
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int chunk = (int)blockIdx.x * 4 + wave;
+    const int n_chunks = (a.n + a.vc - 1) / a.vc;
+    if (chunk >= n_chunks) return;                   // whole wave
+    if (a.skip != nullptr && *a.skip == 0) return;   // uniform
+    const unsigned bstride = (unsigned)a.B * 4u;     // bytes per variable row
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(a.x), (short)0,
+                                                                          (int)a.x_bytes, BUF_DW3);
+    int bl[RPL], lo[RPL];   // restart of each 64-block, and its load offset (clamped into the row)
+    bool bok[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        bl[r] = ((int)blockIdx.y * RPL + r) * 64 + lane;
+        bok[r] = bl[r] < a.B;
+        lo[r] = (bok[r] ? bl[r] : a.B - 1) * 4;
+    }
+    const int v0 = chunk * a.vc;
+    const int nv = min(a.vc, a.n - v0);
+    const int pb = lane <= nv ? pptr[v0 + lane] : 0;
+    const int sb = lane <= nv ? vptr[v0 + lane] : 0;
+    float facc[RPL];
+    int nuns[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        facc[r] = 0.f;
+        nuns[r] = 0;
+    }
+    const float eta = STEP ? (a.eta_dev != nullptr ? *a.eta_dev : a.eta) : 0.f;
+#pragma unroll 1
+    for (int j = 0; j < nv; ++j) {
+        const unsigned row = (unsigned)(v0 + j) * bstride;
+        float xv[RPL];
+        double acc[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            xv[r] = ldf(rx, lo[r], row);
+            acc[r] = 0.0;
+        }
+        // the other constraints' slots, ascending slot order
+        const int e0 = lane_bcast(sb, j), e1 = lane_bcast(sb, j + 1);
+#pragma unroll 1
+        for (int e = e0; e < e1; e += NS) {
+            const int idx = lane < NS && e + lane < e1 ? vslot[e + lane] : 0;
+            float sv[NS][RPL];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                // the slot buffer may pass 2^31 bytes: 64-bit addresses
+                const float *srow = a.slot + (size_t)lane_bcast(idx, q) * (size_t)a.B;
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) sv[q][r] = srow[lo[r] >> 2];
+            }
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const bool in = e + q < e1;   // uniform
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) acc[r] += in ? (double)sv[q][r] : 0.0;
+            }
+        }
+        // pulled entries, list order
+        const int p0 = lane_bcast(pb, j), p1 = lane_bcast(pb, j + 1);
+#pragma unroll 1
+        for (int p = p0; p < p1; p += NB) {
+            const int w = p * E + lane;
+            const int ev = lane < NB * E ? (w < p1 * E ? pent[w] : ((lane % E) == 1 ? RK_NULL : 0)) : 0;
+            float xo[NB][NO][RPL];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+#pragma unroll
+                for (int t = 0; t < NO; ++t) {
+                    const unsigned so = (unsigned)(lane_bcast(ev, q * E + 2 + t) & 0x7fffffff) * bstride;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r)
+                        xo[q][t][r] = ldf(rx, lo[r], so);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int orig = lane_bcast(ev, q * E);
+                const int meta = lane_bcast(ev, q * E + 1);
+                const int rk = meta & 7;
+                const int km1 = (meta >> 3) & 7;
+                const bool own_neg = (meta >> 10) & 1;
+                const float al = rkt[rk], be = rkt[8 + rk], c1 = rkt[24 + rk];
+                const float wc = wts[orig];
+                float prod[RPL];
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) prod[r] = 1.f;
+#pragma unroll
+                for (int t = 0; t < NO; ++t) {
+                    if (t < km1) {   // uniform
+                        const bool neg = lane_bcast(ev, q * E + 2 + t) < 0;
+#pragma unroll
+                        for (int r = 0; r < RPL; ++r) {
+                            const float xval = xo[q][t][r];
+                            prod[r] *= __builtin_fmaf(be, neg ? -xval : xval, al);
+                        }
+                    }
+                }
+                const float wc1 = wc * c1;
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    const float gterm = wc1 * prod[r];
+                    acc[r] += (double)(own_neg ? -gterm : gterm);
+                }
+                if ((meta >> 11) & 1) {   // first literal of the constraint: value and check
+                    const float c0 = rkt[16 + rk], cst = rkt[32 + rk];
+                    int nbad = 0;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) {
+                        const float lown = own_neg ? -xv[r] : xv[r];
+                        const float we = __builtin_fmaf(c0, prod[r] * __builtin_fmaf(be, lown, al), cst);
+                        facc[r] = __builtin_fmaf(wc, we, facc[r]);
+                        if (a.want_check) {
+                            // true literals (x < 0 is True; a negated literal flips it)
+                            int c = (own_neg != (xv[r] < 0.f)) ? 1 : 0;
+#pragma unroll
+                            for (int t = 0; t < NO; ++t)
+                                if (t < km1) c += ((lane_bcast(ev, q * E + 2 + t) < 0) != (xo[q][t][r] < 0.f)) ? 1 : 0;
+                            const int chk = ((meta >> 6) & 15) - 2;
+                            const bool sat = chk >= 0 ? (c >= chk) : ((c & 1) == (chk == -2 ? 1 : 0));
+                            const bool uns = !sat && bok[r];
+                            nuns[r] += uns ? 1 : 0;
+                            if (a.unsat_bits != nullptr && uns)
+                                atomicOr(&a.unsat_bits[(size_t)bl[r] * a.wm + (orig >> 5)], 1u << (orig & 31));
+                            nbad += (int)__popcll(__ballot(uns));
+                        }
+                    }
+                    if (a.U != nullptr && a.want_check && lane == 0 && nbad > 0) atomicAdd(&a.U[orig], nbad);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            if (!bok[r]) continue;
+            const size_t idx = (size_t)(v0 + j) * (size_t)a.B + (size_t)bl[r];
+            const float g = (float)acc[r];
+            if constexpr (STEP) {
+                // same rounding as the gradient, then the projected step
+                const float y = __builtin_fmaf(-eta, g, xv[r]);
+                a.x_out[idx] = fminf(fmaxf(y, -1.0f), 1.0f);
+            } else {
+                a.grad[idx] = g;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        if (!bok[r]) continue;
+        const size_t rowi = (size_t)(a.row0 + chunk) * (size_t)a.B + (size_t)bl[r];
+        a.fpart[rowi] = facc[r];
+        if (a.want_check) a.cpart[rowi] = nuns[r];
+    }
+}
+
+template <int E, int RPL>
+static void launch_pull_t(const PullArgs &a, hipStream_t s)
+{
+    const int chunks = (a.n + a.vc - 1) / a.vc;
+    const dim3 grid((unsigned)((chunks + 3) / 4), (unsigned)((a.B + 64 * RPL - 1) / (64 * RPL)));
+    if (a.x_out)
+        hipLaunchKernelGGL((k_pull<E, RPL, true>), grid, dim3(256), 0, s, a, a.rk, a.w, a.pent, a.pptr, a.vslot, a.vptr);
+    else
+        hipLaunchKernelGGL((k_pull<E, RPL, false>), grid, dim3(256), 0, s, a, a.rk, a.w, a.pent, a.pptr, a.vslot, a.vptr);
+}
+
+hipError_t launch_pull(int E, const PullArgs &a, hipStream_t s)
+{
+    if (a.n <= 0 || a.B <= 0) return hipSuccess;
+    if ((a.x_out == nullptr) == (a.grad == nullptr) || a.x_out == a.x) return hipErrorInvalidValue;
+    if (a.vc < 1 || a.vc > PULL_VC_MAX || a.x_bytes > 0x7fffffffll) return hipErrorInvalidValue;
+    // restarts per lane: as many 64-blocks as the batch fills, up to 4
+    const int rpl = a.B > 192 ? 4 : (a.B > 64 ? 2 : 1);
+    if (E == 4) {
+        if (rpl == 4) launch_pull_t<4, 4>(a, s);
+        else if (rpl == 2) launch_pull_t<4, 2>(a, s);
+        else launch_pull_t<4, 1>(a, s);
+    } else if (E == 8) {
+        if (rpl == 4) launch_pull_t<8, 4>(a, s);
+        else if (rpl == 2) launch_pull_t<8, 2>(a, s);
+        else launch_pull_t<8, 1>(a, s);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_copy_f32(float *dst, const float *src, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+}  // namespace ffsat
