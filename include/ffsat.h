@@ -215,6 +215,21 @@ ffsat_status ffsat_eval_step(ffsat_plan *plan, float *x, float eta, float *F, in
 /* Same as ffsat_eval with double buffers and FP64 computation throughout. */
 ffsat_status ffsat_eval_f64(ffsat_plan *plan, const double *x, double *F, double *grad,
                             double *con_val, void *stream);
+/* ffsat_eval's F and grad for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no plan, no allocation and no allocating library call.  The
+ * per-literal slots, objective rows and their partial sums live in a fixed
+ * 64 MiB device array of the library (one per device, held until the
+ * process ends), so 4 * (nnz * B + rows * B + ceil(rows / 64) * B) bytes,
+ * each term rounded up to 256, must fit (rows <= the number of
+ * constraints); larger calls return FFSAT_E_UNSUPPORTED before any launch.
+ * x, F ([B], optional) and grad ([n][B], optional) are device buffers of the
+ * problem's device, which must be current.  Bins run one after another on
+ * `stream` in the problem's default tile shapes; results equal ffsat_eval's
+ * up to the grouping of the FP32 sums.  Every call on a device uses the
+ * same array: calls that overlap on one device race. */
+ffsat_status ffsat_eval_noalloc(const ffsat_problem *problem, int32_t B, const float *x, float *F,
+                                float *grad, void *stream);
 
 /* ---- projected step (App. A.3, Alg. 5, clip to [-1,1]) ------------------- */
 

@@ -77,6 +77,7 @@ _SIGS = {
     "ffsat_eval": (I32, [P, P, P, P, P, P]),
     "ffsat_eval_f64": (I32, [P, P, P, P, P, P]),
     "ffsat_eval_check": (I32, [P, P, P, P, P, P, P, P, P]),
+    "ffsat_eval_noalloc": (I32, [P, I32, P, P, P, P]),
     "ffsat_eval_step": (I32, [P, P, C.c_float, P, P, P, P]),
     "ffsat_step": (I32, [P, P, P, P, C.c_float, P]),
     "ffsat_step_f64": (I32, [P, P, P, P, C.c_double, P]),
