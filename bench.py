@@ -21,8 +21,10 @@ restart) (2 FLOP each) against the published vector peak of their
 arithmetic type (FP32 157.3, FP64 78.6 TFLOP/s); transform-free chains and
 the reduction move 8 B per (literal, restart) in the evaluation (a gathered
 point, a slot written) plus 4 B per (literal, restart) and 8 B per
-(variable, restart) in the reduction, against 8 TB/s; a kernel is bound by
-whichever of the two its work needs longer on.  Hardware counters of the
+(variable, restart) in the reduction; the pulled gradient moves 4 B per
+gathered other literal and per remaining slot, 8 B per (variable, restart)
+and its entry lists; all against 8 TB/s.  A kernel is bound by whichever of
+the two its work needs longer on.  Hardware counters of the
 same kernel (VALU instructions, HBM bytes) come from the committed rocprofv3
 summary in profiles/ while the kernel sources are unchanged.
 
@@ -36,6 +38,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import platform
 import sys
@@ -129,22 +132,20 @@ def roofline_entry(label, flop, nbytes, dt, avg_s, launches_per_step):
     return ent
 
 
-def kernel_card(workload):
-    """Counters of the workload's dominant kernel from the committed rocprofv3
-    summary (profiles/<workload>_counters.txt), if the kernel sources hash to
-    the value recorded with them; else None."""
+def kernel_card(workload, kernel_name):
+    """Counters of one kernel from the committed rocprofv3 summary
+    (profiles/<workload>_counters.txt, its `card:` lines), if the library
+    sources hash to the value recorded with them; else None."""
     from paper_2308_15020_amd.profsum import kernel_source_hash
     path = os.path.join(ROOT, "profiles", f"{workload}_counters.txt")
     if not os.path.exists(path):
         return None
-    kv = {}
     for line in open(path):
-        if ":" in line and not line.startswith(" "):
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != kernel_source_hash():
-        return None
-    return kv
+        if line.startswith("card: "):
+            c = json.loads(line[len("card: "):])
+            if c.get("kernel_name") == kernel_name and c.get("source_sha256") == kernel_source_hash():
+                return c
+    return None
 
 
 def measure(name, args, dev, headline):
@@ -234,6 +235,24 @@ def measure(name, args, dev, headline):
             ent = roofline_entry(label, flop, nbytes, dt, avg_s, per_step)
             ent["kernel_name"] = (f"k_eval<float, {'double' if bd['ct'] == 'f64' else 'float'}, {bd['seg']}, "
                                   f"{bd['L']}, {'true' if bd['class'] == 'dft' else 'false'}>")
+        elif k["bin"] == -3:
+            # pulled gradient: the other literals of every pulled occurrence
+            # gathered, the remaining slots read, the entry lists read once per
+            # 64 * rpl restarts, x read and the stepped x written, one objective
+            # and one count row per chunk written
+            rpl = 4 if B > 192 else (2 if B > 64 else 1)
+            nbytes = (4.0 * desc["pull_gathers_per_restart"] * B + 4.0 * desc["pull_other_slots"] * B
+                      + desc["pull_entries"] * desc["pull_entry_bytes"] * math.ceil(B / (64 * rpl))
+                      + 8.0 * inst.n_vars * B + 8.0 * desc["pull_chunks"] * B)
+            ent = roofline_entry(f"pulled gradient + projected step (transform-free constraints of length <= "
+                                 f"{desc['pull']}: {desc['pull_entries']} occurrences, "
+                                 f"{desc['pull_gathers_per_restart']} gathers per restart; "
+                                 f"{desc['pull_other_slots']} other slots)", 0.0, nbytes, "f32", avg_s, per_step)
+            ent["kernel_name"] = f"k_pull<{desc['pull_entry_bytes'] // 4}, {rpl}, true>"
+        elif desc["pull"]:
+            nbytes = 8.0 * desc["objective_rows"] * B
+            ent = roofline_entry("objective and count row sums", 0.0, nbytes, "f32", avg_s, per_step)
+            ent["kernel_name"] = "k_reduce<float, false>"
         else:
             nbytes = (4.0 * inst.nnz + 8.0 * inst.n_vars) * B
             ent = roofline_entry("gradient reduction + projected step", 0.0, nbytes, "f32", avg_s, per_step)
@@ -265,18 +284,18 @@ def measure(name, args, dev, headline):
     kernels.sort(key=lambda e: -e["ms_per_step"])
     dom = dict(kernels[0])
     dom["traffic"] = None
-    card = kernel_card(name)
-    if card is not None and card.get("kernel_name") == dom["kernel_name"]:
+    card = kernel_card(name, dom["kernel_name"])
+    if card is not None:
         if "traffic_bytes_per_launch" in card:
             dom["traffic"] = float(card["traffic_bytes_per_launch"])
             dom["traffic_to_algorithmic_bytes"] = dom["traffic"] / max(dom["bytes_per_launch"], 1.0)
+        if "rocprof_avg_us" in card:
+            dom["rocprof_avg_launch_ms"] = float(card["rocprof_avg_us"]) / 1e3
         if "valu_insts_per_launch" in card:
             vi = float(card["valu_insts_per_launch"])
             # wave64 VALU instructions issue one per 4 cycles per SIMD
-            dom["valu_issue"] = vi * 4.0 / (SIMDS * CLOCK_GHZ * 1e9 * dom["avg_launch_ms"] / 1e3)
             dom["valu_insts_per_launch"] = vi
-        if "rocprof_avg_us" in card:
-            dom["rocprof_avg_launch_ms"] = float(card["rocprof_avg_us"]) / 1e3
+            dom["valu_issue"] = vi * 4.0 / (SIMDS * CLOCK_GHZ * 1e9 * dom["avg_launch_ms"] / 1e3)
     for e in kernels:
         for key in ("flop_per_launch", "bytes_per_launch", "achieved", "frac", "avg_launch_ms", "ms_per_step"):
             if key in e and isinstance(e[key], float):
@@ -284,7 +303,10 @@ def measure(name, args, dev, headline):
     res = {"workload": wl["desc"].format(B=B), "n_vars": inst.n_vars, "n_cons": inst.m, "nnz": inst.nnz,
            "restarts": B, "steps": steps, "warmup": warmup, "ms_per_step": ms_per_step, "value": value,
            "iterations_per_graph_replay": chunk, "setup_s_incl_autotune": setup_s,
-           "best_n_sat_last_step": n_sat_last, "roofline": dom, "kernels": kernels[:12]}
+           "best_n_sat_last_step": n_sat_last,
+           "plan": {"launch_structure": desc["mode"], "pull_max_len": desc["pull"],
+                    "tuned_candidates_ms": desc.get("tuned_modes")},
+           "roofline": dom, "kernels": kernels[:12]}
     out = (res, inst, x_np)
     plan.close()
     prob.close()
@@ -457,6 +479,7 @@ def main():
                    "step": "objective + gradient + exact round-and-check of x_t (one pass), projected step, "
                            "ERWA weight update; graph-replayed",
                    "iterations_per_graph_replay": head["iterations_per_graph_replay"],
+                   "plan": head["plan"],
                    "setup_s_incl_autotune": round(head["setup_s_incl_autotune"], 2)},
         "roofline": head["roofline"],
         "kernels": head["kernels"],

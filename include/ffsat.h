@@ -175,7 +175,8 @@ ffsat_status ffsat_plan_describe(const ffsat_plan *plan, char *buf, size_t len);
 /* Kernel timing: while on, every evaluation-kernel launch and every
  * reduction launch made by ffsat_eval / ffsat_eval_f64 / ffsat_run_steps
  * (eager, not graph replays) is bracketed by HIP events on the caller's
- * stream.  ffsat_plan_profile_read synchronises on those events and writes
+ * stream, and the bins run one after another on that stream (no side
+ * streams), so that each launch's time is its own.  ffsat_plan_profile_read synchronises on those events and writes
  * JSON {"kernels": [{"io", "bin", "launches", "total_ms", "avg_ms"}]} into
  * buf (truncated to len-1, NUL-terminated); reset != 0 clears the sums. */
 ffsat_status ffsat_plan_profile(ffsat_plan *plan, int32_t on);

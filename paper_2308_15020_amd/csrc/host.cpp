@@ -158,7 +158,14 @@ static std::vector<float> rkind_table()
 // the removed factor e^{i k th/2} C^k (or S^k), the padding literals of the
 // segment layout (value +1, count-neutral) and the power-of-two start value
 // of every segment are folded into c0 / c1 here, in long double.
-TypeD dft_type(const std::vector<cld> &hv, int k, int L, int s)
+//
+// FP64 tables (f64 = true) run every frequency with form 1's factor code:
+// a form-2 factor is kappa (1 - i l / kappa), kappa = C/S, so its lane
+// multiplies by 1 - i (S/C) l starting from kappa^s times the usual start
+// value; each segment product is then exactly the form-2 one (FP64 holds
+// kappa^s, >= 1e-41 for k <= 512), and the leave-one-out products carry one
+// extra factor kappa, divided out of c1.  3 FP64 ops per factor instead of 4.
+TypeD dft_type(const std::vector<cld> &hv, int k, int L, int s, bool f64)
 {
     TypeD t;
     t.cls = CLASS_DFT;
@@ -185,6 +192,14 @@ TypeD dft_type(const std::vector<cld> &hv, int k, int L, int s)
         for (int q = 0; q < npad; ++q) corr /= psipad;
         const cld c0 = 2.0L * h * sigma * corr * ldexpl(1.0L, L * e);
         const cld c1 = c0 * (form1 ? cld(0.0L, -tk) : cld(0.0L, -1.0L));
+        if (f64 && !form1) {
+            // form 2 through form 1's code (see above)
+            const cld c1r = c1 / tk;
+            FreqD fd{(double)(1.0L / tk), (double)(ldexpl(1.0L, -e) * powl(tk, (long double)s)), (double)c0.real(),
+                     (double)c0.imag(), (double)c1r.real(), (double)c1r.imag()};
+            f1.push_back(fd);
+            continue;
+        }
         FreqD fd{(double)tk, (double)ldexpl(1.0L, -e), (double)c0.real(), (double)c0.imag(),
                  (double)c1.real(), (double)c1.imag()};
         (form1 ? f1 : f2).push_back(fd);
@@ -651,6 +666,8 @@ static ffsat_status build_pull(ffsat_problem *p, int c)
     if (!vslot.empty() && (st = upload(&P.d_vslot, vslot, p->device_bytes)) != FFSAT_OK) return st;
     if ((st = upload(&P.d_rk, rkind_table(), p->device_bytes)) != FFSAT_OK) return st;
     P.n_ent = pptr[(size_t)n];
+    P.n_rest = vptr[(size_t)n];
+    for (int64_t e = 0; e < P.n_ent; ++e) P.n_gather += ((pent[(size_t)e * E + 1] >> 3) & 7);
     P.built = true;
     return FFSAT_OK;
 }
@@ -713,7 +730,7 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
                 auto mh = memo.find(key);
                 if (mh == memo.end())
                     mh = memo.emplace(key, uc ? uc_coeffs(tk.kind, tk.param, k) : conj_coeffs(tk.kind, tk.param, k)).first;
-                td = uc ? uc_type(mh->second, k, L, seg) : dft_type(mh->second, k, L, seg);
+                td = uc ? uc_type(mh->second, k, L, seg) : dft_type(mh->second, k, L, seg, ct == CT_F64);
             }
             else if (rk == RK_OR) td = real_or();
             else if (rk == RK_XOR) td = real_xor(rparam);
@@ -1198,7 +1215,8 @@ static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream
             // grouped launch when there is one, else before it
             hipError_t e;
             hipStream_t ss = s;
-            const bool fork = pl->side[0] != nullptr && !pl->gsolo.empty();
+            // while profiling, everything runs on s: each launch's time is its own
+            const bool fork = pl->side[0] != nullptr && !pl->gsolo.empty() && !pl->profiling;
             if (fork) {
                 if ((e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return e;
                 if ((e = hipStreamWaitEvent(pl->side[0], pl->ev_fork, 0)) != hipSuccess) return e;
@@ -1237,7 +1255,7 @@ static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream
             return hipSuccess;
         }
     }
-    const bool fork = pl->side[0] != nullptr && bins.size() > 1;
+    const bool fork = pl->side[0] != nullptr && bins.size() > 1 && !pl->profiling;
     hipError_t e;
     constexpr int NS = ffsat_plan::N_SIDE + 1;   // slot 0 is the caller's stream
     double load[NS] = {};
@@ -1444,28 +1462,37 @@ static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cach
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        float best = 1e30f;
         std::vector<int> modes = pl->mode_auto ? std::vector<int>{MODE_GROUP_DFT, MODE_GROUP_ALL, MODE_PER_BIN}
                                                : std::vector<int>{pl->mode};
         std::vector<int> pulls = pl->pull_auto ? std::vector<int>{PULL_OFF, PULL_LE3, PULL_LE7}
                                                : std::vector<int>{pl->pull};
-        std::vector<std::pair<int, int>> tried;
-        for (int m : modes) {
+        // distinct (launch structure, pull class) candidates after normalisation
+        std::vector<std::pair<int, int>> cands;
+        for (int m : modes)
             for (int c : pulls) {
                 pl->mode = m;
-                pl->grouped = m != MODE_PER_BIN;
                 ffsat_status st = set_pull(pl, c);
                 if (st != FFSAT_OK) return st;
                 const std::pair<int, int> cand{m, pl->pull};
-                if (std::find(tried.begin(), tried.end(), cand) != tried.end()) continue;
-                tried.push_back(cand);
+                if (std::find(cands.begin(), cands.end(), cand) == cands.end()) cands.push_back(cand);
+            }
+        // two sweeps over the candidates (a warm-up evaluation, then three
+        // timed ones each); a candidate's time is its faster sweep, so that a
+        // slow moment of the device does not decide the choice
+        std::vector<float> tbest(cands.size(), 1e30f);
+        for (int sweep = 0; sweep < 2; ++sweep) {
+            for (size_t i = 0; i < cands.size(); ++i) {
+                pl->mode = cands[i].first;
+                pl->grouped = pl->mode != MODE_PER_BIN;
+                ffsat_status st = set_pull(pl, cands[i].second);
+                if (st != FFSAT_OK) return st;
                 if ((st = build_groups(pl)) != FFSAT_OK) return st;
                 float *out = pl->pull ? pl->d_xalt : nullptr;
                 if ((st = run_eval<float>(pl, pl->d_scratch_x, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                           true, pl->d_scratch_x, 0.f, s, nullptr, nullptr, out)) != FFSAT_OK)
                     return st;
                 HIPCHK(hipEventRecord(e0, s));
-                const int reps = 5;
+                const int reps = 3;
                 for (int r = 0; r < reps; ++r)
                     if ((st = run_eval<float>(pl, pl->d_scratch_x, nullptr, nullptr, nullptr, nullptr, nullptr,
                                               nullptr, true, pl->d_scratch_x, 0.f, s, nullptr, nullptr, out)) !=
@@ -1475,13 +1502,19 @@ static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cach
                 HIPCHK(hipEventSynchronize(e1));
                 float ms = 0.f;
                 HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best * 0.97f) {
-                    best = ms;
-                    best_mode = m;
-                    best_pull = pl->pull;
-                }
+                tbest[i] = std::min(tbest[i], ms / reps);
             }
         }
+        // the fastest; an earlier candidate keeps the choice within 2 %
+        size_t bi = 0;
+        for (size_t i = 1; i < cands.size(); ++i)
+            if (tbest[i] < tbest[bi] * 0.98f) bi = i;
+        best_mode = cands[bi].first;
+        best_pull = cands[bi].second;
+        std::ostringstream lg;
+        for (size_t i = 0; i < cands.size(); ++i)
+            lg << (i ? ", " : "") << "[" << cands[i].first << ", " << PULL_K[cands[i].second] << ", " << tbest[i] << "]";
+        pl->tune_log = lg.str();
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         cache[key] = Shape{best_mode, best_pull, 1};   // mode in the cpw field, pull class in wpb
@@ -1734,6 +1767,8 @@ extern "C" ffsat_status ffsat_plan_destroy(ffsat_plan *pl)
     return FFSAT_OK;
 }
 
+static int eval_rows(const ffsat_plan *pl, int io, int pull);
+
 extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, size_t len)
 {
     if (!pl || !buf || len == 0) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
@@ -1745,7 +1780,13 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
       << ", \"solo_bins\": " << pl->gsolo.size() << ", \"graphs_cached\": " << pl->graphs.size()
       << ", \"graph_captures\": " << pl->captures << ", \"pull\": " << PULL_K[pl->pull]
       << ", \"pull_auto\": " << (pl->pull_auto ? "true" : "false") << ", \"pull_vc\": " << pl->pull_vc
-      << ", \"pull_entries\": " << (pl->pull ? pl->p->lay[IO_F32].pull[pl->pull].n_ent : 0) << ", \"bins\": {";
+      << ", \"pull_entries\": " << (pl->pull ? pl->p->lay[IO_F32].pull[pl->pull].n_ent : 0)
+      << ", \"pull_entry_bytes\": " << (pl->pull ? 4 * PULL_E[pl->pull] : 0)
+      << ", \"pull_gathers_per_restart\": " << (pl->pull ? pl->p->lay[IO_F32].pull[pl->pull].n_gather : 0)
+      << ", \"pull_other_slots\": " << (pl->pull ? pl->p->lay[IO_F32].pull[pl->pull].n_rest : 0)
+      << ", \"pull_chunks\": " << (pl->pull ? (pl->p->n + pl->pull_vc - 1) / pl->pull_vc : 0)
+      << ", \"objective_rows\": " << eval_rows(pl, IO_F32, pl->pull)
+      << ", \"tuned_modes\": [" << pl->tune_log << "], \"bins\": {";
     for (int io = 0; io < 2; ++io) {
         o << (io ? ", " : "") << "\"" << (io ? "f64" : "f32") << "\": [";
         for (size_t i = 0; i < pl->bins[io].size(); ++i) {
@@ -1902,20 +1943,25 @@ static ffsat_status run_eval(ffsat_plan *pl, const IO *x, IO *F, IO *grad, IO *c
     HIPCHK(enqueue_bins<IO>(pl, io, a, s, pull ? pull : 3));
     ReduceArgs<IO> r = reduce_args<IO>(pl, io, do_value ? grad : nullptr, do_value ? x_step : nullptr, eta, eta_dev,
                                        skip, do_value ? F : nullptr, n_sat, pull);
+    // profile records: -3 the pulled gradient, -1 the reduction (with the
+    // pull path only the objective / count sums)
     ProfRec rec;
-    prof_begin(pl, s, prof_active(pl, s), rec, io, -1);
     hipError_t e = hipSuccess;
     if constexpr (sizeof(IO) == 4) {
         if (pull) {
             float *out = nullptr;
             if (x_step) out = x_next ? x_next : pl->d_xalt;
+            prof_begin(pl, s, prof_active(pl, s), rec, io, -3);
             e = enqueue_pull(pl, (const float *)x, x_step ? nullptr : (float *)grad, out, eta, eta_dev, unsat_bits, U,
                              want_check, skip, s);
+            prof_end(pl, s, rec);
             if (e == hipSuccess && x_step && !x_next)
                 e = launch_copy_f32(x_step, pl->d_xalt, (int64_t)p->n * pl->B, s);
         }
+        prof_begin(pl, s, prof_active(pl, s), rec, io, -1);
         if (e == hipSuccess) e = launch_reduce_f32(r, s);
     } else {
+        prof_begin(pl, s, prof_active(pl, s), rec, io, -1);
         e = launch_reduce_f64(r, s);
     }
     prof_end(pl, s, rec);

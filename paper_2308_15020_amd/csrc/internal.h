@@ -84,6 +84,8 @@ constexpr int PULL_VC_MAX = 8;   // variables per wave of k_pull (its LDS holds 
 struct PullLayout {
     bool built = false;
     int64_t n_ent = 0;           // pulled (literal occurrence) entries
+    int64_t n_gather = 0;        // other literals over all entries (gathers per restart)
+    int64_t n_rest = 0;          // slots of the other constraints
     int32_t *d_pptr = nullptr;   // [n+1] variable -> first entry
     int32_t *d_pent = nullptr;   // [n_ent][PULL_E[c]]
     int32_t *d_vptr = nullptr;   // [n+1] variable-major transpose of the remaining slots
@@ -260,6 +262,7 @@ struct ffsat_plan {
     bool pull_auto = false;
     int pull_vc = 8;                 // variables per wave of k_pull
     float *d_xalt = nullptr;         // [n][B] second point buffer of in-place pulled steps
+    std::string tune_log;            // [launch structure, pull length, ms per evaluation] per tuned candidate
     int64_t captures = 0;            // graphs captured over the plan's life
     int64_t device_bytes = 0;
     bool profiling = false;

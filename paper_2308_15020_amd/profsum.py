@@ -10,6 +10,9 @@
       --copy-mib, the same counters for the largest plain copy dispatch and
       the factor (M MiB / counter) that turns FETCH_SIZE / WRITE_SIZE into
       bytes
+  python -m paper_2308_15020_amd.profsum cards <trace csv> --sq <csv> --fetch <csv> --write <csv>
+      --copy-mib M --kernels "k_pull<4| 4| true>,..."
+      one JSON card per kernel template (see cards())
 """
 from __future__ import annotations
 
@@ -70,15 +73,63 @@ def pmc(path: str, copy_mib: float = 0.0, top: int = 25) -> str:
 
 
 def kernel_source_hash() -> str:
-    """SHA-256 over the sources that make up the evaluation kernels."""
+    """SHA-256 over every device and host source of the library (a change to
+    any kernel, or to how it is launched, invalidates recorded counters)."""
     import hashlib
     import os
     here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     h = hashlib.sha256()
-    for f in ("eval_kernel.h", "eval_group.hip", "eval_f32.hip", "internal.h"):
-        with open(os.path.join(here, f), "rb") as fh:
-            h.update(fh.read())
+    for f in sorted(os.listdir(here)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(here, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def _by_template(path, counter=None):
+    """Per kernel template name: (sum of values or durations, dispatches)."""
+    acc = defaultdict(float)
+    calls = defaultdict(set)
+    for r in csv.DictReader(open(path)):
+        name = short(r["Kernel_Name"])
+        if counter is None:
+            acc[name] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            calls[name].add(r.get("Dispatch_Id", r.get("Correlation_Id", len(calls[name]))))
+        elif r["Counter_Name"] == counter:
+            acc[name] += float(r["Counter_Value"])
+            calls[name].add(r["Dispatch_Id"])
+    return {k: (acc[k], len(calls[k])) for k in acc}
+
+
+def cards(trace_csv, sq_csv, fetch_csv, write_csv, copy_mib, kernels):
+    """One `card:` line (JSON) per kernel template: rocprof average duration
+    (kernel trace), VALU instructions and VALU-active cycles per dispatch (SQ
+    pass), HBM bytes per dispatch from FETCH_SIZE and WRITE_SIZE scaled by the
+    plain elementwise kernel of copy_mib MiB, and the sources' hash."""
+    import json
+    tr = _by_template(trace_csv)
+    vi = _by_template(sq_csv, "SQ_INSTS_VALU")
+    va = _by_template(sq_csv, "SQ_ACTIVE_INST_VALU")
+    fe = _by_template(fetch_csv, "FETCH_SIZE")
+    wr = _by_template(write_csv, "WRITE_SIZE")
+    sf, sw = _calib(fetch_csv, "FETCH_SIZE", copy_mib), _calib(write_csv, "WRITE_SIZE", copy_mib)
+    out = []
+    for k in kernels:
+        c = {"kernel_name": k, "source_sha256": kernel_source_hash()}
+        if k in tr:
+            c["rocprof_avg_us"] = round(tr[k][0] / tr[k][1], 2)
+            c["rocprof_dispatches"] = tr[k][1]
+        if k in vi:
+            c["valu_insts_per_launch"] = round(vi[k][0] / vi[k][1], 1)
+        if k in va:
+            c["valu_active_per_launch"] = round(va[k][0] / va[k][1], 1)
+        if k in fe and k in wr and sf and sw:
+            rb = fe[k][0] / fe[k][1] * 1024 * sf
+            wb = wr[k][0] / wr[k][1] * 1024 * sw
+            c.update({"read_bytes_per_launch": round(rb), "write_bytes_per_launch": round(wb),
+                      "traffic_bytes_per_launch": round(rb + wb)})
+        out.append("card: " + json.dumps(c))
+    return "\n".join(out)
 
 
 def _per_dispatch(path, counter, match):
@@ -124,13 +175,21 @@ def traffic(fetch_csv, write_csv, kernel, copy_mib):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("kind", choices=["trace", "pmc", "traffic"])
+    ap.add_argument("kind", choices=["trace", "pmc", "traffic", "cards"])
     ap.add_argument("csv")
     ap.add_argument("csv2", nargs="?", default=None, help="traffic: the WRITE_SIZE csv")
     ap.add_argument("--copy-mib", type=float, default=0.0)
     ap.add_argument("--kernel", default="k_eval_group")
     ap.add_argument("--top", type=int, default=25)
+    ap.add_argument("--sq", default=None, help="cards: the SQ counter csv")
+    ap.add_argument("--fetch", default=None, help="cards: the FETCH_SIZE csv")
+    ap.add_argument("--write", default=None, help="cards: the WRITE_SIZE csv")
+    ap.add_argument("--kernels", default="", help="cards: comma-separated kernel template names ('|' inside)")
     a = ap.parse_args()
+    if a.kind == "cards":
+        ks = [k.replace("|", ",") for k in a.kernels.split(",") if k]
+        print(cards(a.csv, a.sq, a.fetch, a.write, a.copy_mib, ks))
+        return
     if a.kind == "trace":
         print(trace(a.csv, a.top))
     elif a.kind == "pmc":
