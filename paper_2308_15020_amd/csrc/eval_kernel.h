@@ -303,15 +303,21 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
     // FP64 bounded-basis frequencies over several lanes: whole product by a
     // butterfly, then a division (no scans)
     constexpr bool ALLRED = sizeof(CT) == 8 && L >= 2 && FORM != 3;
+    // FP64 form-1 factors of short segments: the reverse pass reuses the
+    // forward pass's tau * l (2 more VGPRs per position, one FP64 multiply
+    // less per position and frequency)
+    constexpr bool KEEP_U = sizeof(CT) == 8 && FORM == 1 && SEG <= 16;
     (void)j;
     const CT tk = fr.tk;
     CT pr[SEG], pi[SEG];
+    CT uk[KEEP_U ? SEG : 1];
     CT Pr = fr.init, Pi = 0;
 #pragma unroll
     for (int t = 0; t < SEG; ++t) {
         pr[t] = Pr; pi[t] = Pi;
         if constexpr (FORM == 1) {
             const CT u = tk * lv[t];
+            if constexpr (KEEP_U) uk[t] = u;
             const CT nr = fmaT(Pi, u, Pr);
             const CT ni = fmaT(-Pr, u, Pi);
             Pr = nr; Pi = ni;
@@ -361,7 +367,9 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
         gr[t] = fmaT(pr[t], Sr, fmaT(-pi[t], Si, gr[t]));
         if (t > 0) {
             if constexpr (FORM == 1) {
-                const CT u = tkb * lv[t];
+                CT u;
+                if constexpr (KEEP_U) u = uk[t];
+                else u = tkb * lv[t];
                 const CT nr = fmaT(Si, u, Sr);
                 const CT ni = fmaT(-Sr, u, Si);
                 Sr = nr; Si = ni;
