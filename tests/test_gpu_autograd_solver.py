@@ -138,6 +138,45 @@ def test_time_to_solve_harness_runs(ffs):
     assert 0 <= c["instances"] <= 2 and (c["instances"] == 0 or c["learned_s"] > 0)
 
 
+def test_learned_initialisation_needs_fewer_rounds(ffs):
+    """What the trained network gains over the method without it, counted in
+    rounds (deterministic: fixed seeds, deterministic kernels).  Leak-free
+    family shaped like the mixed n = 2000 workload (OR clauses satisfied by
+    the hidden assignment and its complement, XOR parities from it,
+    at-least-t signs independent of it) with 400 XOR constraints; a short
+    training run on 16 instances; 6 test instances (seeds disjoint from the
+    training seeds).  An unsolved run counts as rounds + 1.  The learned arm
+    must solve at least as many instances as uniform restarts and need fewer
+    median rounds."""
+    import argparse
+
+    from paper_2308_15020_amd import tts
+    from paper_2308_15020_amd.mpnn import Mpnn, fit, targets_from_solves
+    train = [ffs.Problem(tts.instance(10000 + i, "hidden2", 400), device=0) for i in range(16)]
+    targets = [targets_from_solves(p, B=1024, seed=10000 + i) for i, p in enumerate(train)]
+    net = Mpnn(64, 3, device=0, seed=1)
+    hist = fit(net, train, targets, epochs=20, lr=2e-3)
+    assert hist[-1] < hist[0]
+    args = argparse.Namespace(B=256, rounds=20, T=40, eta=0.3, policy="ROF", frac=0.75, sigma=0.3,
+                              reuse_proposal=True)
+    rounds = {"uniform": [], "learned": []}
+    solved = {"uniform": 0, "learned": 0}
+    for i in range(6):
+        seed = 20000 + i
+        prob = ffs.Problem(tts.instance(seed, "hidden2", 400), device=0)
+        plan = ffs.Plan(prob, args.B)
+        x_buf = torch.empty(prob.n, args.B, dtype=torch.float32, device=DEV)
+        for arm, net_arm in (("uniform", None), ("learned", net)):
+            r = tts.run_arm(prob, plan, net_arm, args, seed, x_buf)
+            solved[arm] += int(r["solved"])
+            rounds[arm].append(r["rounds"] if r["solved"] else args.rounds + 1)
+        plan.close()
+        prob.close()
+    print(solved, rounds)
+    assert solved["learned"] >= solved["uniform"]
+    assert np.median(rounds["learned"]) < np.median(rounds["uniform"])
+
+
 def test_portfolio_arms_keep_their_own_weights(ffs):
     """Two strategies side by side: the run stops when either arm satisfies
     everything (checked by the oracle), the weighting arm's problem has adapted
