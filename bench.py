@@ -66,8 +66,9 @@ WORKLOADS = {
     "large3sat": {"gen": "config3a", "seed": 3000, "B": 256, "steps": 100, "warmup": 10,
                   "desc": "random 3-SAT n=100000, m=420000 (the 3-SAT part of the large instance), "
                           "{B} restarts, FP32"},
-    "uf50": {"gen": "config1", "seed": 1000, "B": 1, "steps": 200, "warmup": 20,
-             "desc": "random 3-SAT n=50, m=213 (latency: one restart), {B} restart(s), FP32"},
+    "uf50": {"gen": "config1", "seed": 1000, "B": 1, "steps": 200, "warmup": 20, "persistent": True,
+             "desc": "random 3-SAT n=50, m=213 (latency: one restart; all iterations of a graph replay in one "
+                     "persistent launch), {B} restart(s), FP32"},
 }
 
 
@@ -165,7 +166,7 @@ def measure(name, args, dev, headline):
     t_setup = time.perf_counter()
     prob = Problem(inst, device=0)
     plan = Plan(prob, B, autotune=not args.no_autotune, tune_cache=args.tune_cache, side_streams=not args.serial,
-                mode=args.mode)
+                mode=args.mode, persistent=wl.get("persistent", False))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
     x0 = torch.from_numpy(x_np).to(dev)
@@ -192,7 +193,8 @@ def measure(name, args, dev, headline):
     plan.profile(False)
 
     # timed loop: chunk fused iterations per graph replay
-    chunk = max(1, min(args.chunk, steps))
+    # the persistent loop runs every timed iteration in one launch
+    chunk = steps if wl.get("persistent") else max(1, min(args.chunk, steps))
     while steps % chunk:
         chunk -= 1
     x.copy_(x0)

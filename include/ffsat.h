@@ -127,7 +127,16 @@ typedef struct {
                                 (the pulled gradient; never with launch structure 2,
                                 never for n * B above 2^29); reserved[3]:
                                 variables per wave of the pulled gradient, 0..8
-                                (0 = 8); others must be 0 */
+                                (0 = 8); reserved[4] = 1: ffsat_run_steps and
+                                ffsat_run_iters run all T iterations in one
+                                persistent launch of one workgroup (points,
+                                gradients, weights, counts and the per-variable
+                                constraint lists in LDS) when every constraint is
+                                transform-free of length <= 7 and 16 n B + 8 m +
+                                4 (n + 1) + 4 E e <= 65024 bytes (e literal
+                                occurrences, E = 4 if every constraint has at
+                                most 3 literals, else 8), else as usual; others
+                                must be 0 */
 } ffsat_plan_opts;
 
 /* ---- errors ------------------------------------------------------------- */

@@ -103,7 +103,7 @@ class Plan:
 
     def __init__(self, problem: Problem, B: int, autotune: bool = False, use_graphs: bool = True,
                  tune_cache: Optional[str] = None, side_streams: bool = True, mode: str = "auto",
-                 pull: str = "auto", pull_vc: int = 0):
+                 pull: str = "auto", pull_vc: int = 0, persistent: bool = False):
         self.problem = problem
         self.B = int(B)
         self.device = problem.device
@@ -124,6 +124,9 @@ class Plan:
             raise ValueError(f"pull must be one of {sorted(pulls)}")
         o.reserved[2] = pulls[pull]
         o.reserved[3] = int(pull_vc)
+        # run_steps as one persistent launch for small problems of short
+        # transform-free constraints (falls back to the usual steps otherwise)
+        o.reserved[4] = 1 if persistent else 0
         h = C.c_void_p()
         check(lib().ffsat_plan_create(problem.handle, self.B, C.byref(o), C.byref(h)))
         self._h = h

@@ -246,20 +246,6 @@ hipError_t launch_assign_bits_f64(int n, int B, const double *x, uint32_t *bits,
 // every block of the update reduces the (at most 1024) partials itself.
 constexpr int ERWA_ONE_BLOCK = 1 << 16;
 
-__device__ __forceinline__ int32_t block_max_1024(int32_t v, int32_t *red)
-{
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    // every lane of every wave ends with the block maximum (counts are >= 0)
-    v = lane < (int)(blockDim.x >> 6) ? red[lane] : 0;
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
-    return v;
-}
-
 __device__ __forceinline__ int32_t strided_max(int m, const int32_t *__restrict__ U, int begin, int stride)
 {
     int32_t mx = 0;
@@ -285,10 +271,7 @@ __global__ __launch_bounds__(1024) void k_erwa_one(int m, const int32_t *__restr
     const int32_t umax = block_max_1024(strided_max(m, U, threadIdx.x, 1024), red);
     const float inv = umax > 0 ? 1.0f / (float)umax : 0.0f;
     const int c = blockIdx.x * 1024 + threadIdx.x;
-    if (c < m) {
-        const float r = umax > 0 ? (float)U[c] * inv : 0.0f;
-        w[c] = (1.0f - alpha) * w[c] + alpha * r;
-    }
+    if (c < m) w[c] = erwa_weight(w[c], U[c], umax, inv, alpha);
 }
 
 __global__ __launch_bounds__(1024) void k_umax_part(int m, const int32_t *__restrict__ U, int32_t *part)
@@ -306,10 +289,8 @@ __global__ __launch_bounds__(1024) void k_erwa_apply(int m, int nparts, const in
     if (alpha_dev != nullptr) alpha = *alpha_dev;
     const int32_t umax = block_max_1024((int)threadIdx.x < nparts ? part[threadIdx.x] : 0, red);
     const float inv = umax > 0 ? 1.0f / (float)umax : 0.0f;
-    for (int c = blockIdx.x * 1024 + threadIdx.x; c < m; c += gridDim.x * 1024) {
-        const float r = umax > 0 ? (float)U[c] * inv : 0.0f;
-        w[c] = (1.0f - alpha) * w[c] + alpha * r;
-    }
+    for (int c = blockIdx.x * 1024 + threadIdx.x; c < m; c += gridDim.x * 1024)
+        w[c] = erwa_weight(w[c], U[c], umax, inv, alpha);
 }
 
 hipError_t launch_erwa(int m, const int32_t *U, float *w, float alpha, const float *alpha_dev, int32_t *part,

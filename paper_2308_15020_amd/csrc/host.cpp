@@ -1638,12 +1638,14 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
     pl->grouped = pl->mode != MODE_PER_BIN;
     const int preq = opts ? opts->reserved[2] : 0;
     const int vc = opts ? opts->reserved[3] : 0;
-    if (preq < 0 || preq > 3 || vc < 0 || vc > PULL_VC_MAX ||
-        (opts && (opts->reserved[4] || opts->reserved[5] || opts->reserved[6] || opts->reserved[7]))) {
+    const int persist = opts ? opts->reserved[4] : 0;
+    if (preq < 0 || preq > 3 || vc < 0 || vc > PULL_VC_MAX || persist < 0 || persist > 1 ||
+        (opts && (opts->reserved[5] || opts->reserved[6] || opts->reserved[7]))) {
         delete pl;
         return fail(FFSAT_E_INVALID_ARG, "reserved[2] (pull) must be in 0..3, reserved[3] (variables per wave) in "
-                                         "0..8, reserved[4..7] must be 0");
+                                         "0..8, reserved[4] (persistent step loop) in 0..1, reserved[5..7] must be 0");
     }
+    pl->persistent = persist == 1;
     pl->pull_auto = preq == 0;
     pl->pull_vc = vc > 0 ? vc : 8;
     default_shapes(pl);
@@ -1669,6 +1671,22 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
         if (e != hipSuccess) st = fail(FFSAT_E_HIP, "side streams: %s", hipGetErrorString(e));
     }
     if (st == FFSAT_OK && !pl->pull_auto) st = set_pull(pl, preq == 1 ? PULL_OFF : (preq == 2 ? PULL_LE7 : PULL_LE3));
+    if (st == FFSAT_OK && pl->persistent) {
+        // eligible: every constraint pulled (transform-free, length <= 7) and
+        // x and the gradient of all (variable, restart) pairs fit in LDS
+        int cmin = PULL_LE3;
+        bool all = !pl->bins[IO_F32].empty();
+        for (const Bin &b : pl->bins[IO_F32]) {
+            all = all && b.pk >= PULL_LE7;
+            cmin = std::min(cmin, b.pk);
+        }
+        if (all && (int64_t)16 * p->n * B + (int64_t)8 * p->m <= ITERS_SMALL_LDS) {
+            st = build_pull(p, cmin);
+            if (st == FFSAT_OK &&
+                iters_small_lds(PULL_E[cmin], p->n, B, p->m, p->lay[IO_F32].pull[cmin].n_ent) <= ITERS_SMALL_LDS)
+                pl->persistent_class = cmin;
+        }
+    }
     if (st == FFSAT_OK) st = build_groups(pl);
     if (st == FFSAT_OK && opts && opts->autotune) {
         st = ffsat_plan_tune(pl, nullptr);
@@ -1786,7 +1804,8 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
       << ", \"pull_other_slots\": " << (pl->pull ? pl->p->lay[IO_F32].pull[pl->pull].n_rest : 0)
       << ", \"pull_chunks\": " << (pl->pull ? (pl->p->n + pl->pull_vc - 1) / pl->pull_vc : 0)
       << ", \"objective_rows\": " << eval_rows(pl, IO_F32, pl->pull)
-      << ", \"tuned_modes\": [" << pl->tune_log << "], \"bins\": {";
+      << ", \"tuned_modes\": [" << pl->tune_log << "], \"persistent_steps\": "
+      << (pl->persistent_class ? "true" : "false") << ", \"bins\": {";
     for (int io = 0; io < 2; ++io) {
         o << (io ? ", " : "") << "\"" << (io ? "f64" : "f32") << "\": [";
         for (size_t i = 0; i < pl->bins[io].size(); ++i) {
@@ -2131,6 +2150,24 @@ static hipError_t enqueue_steps(ffsat_plan *pl, float *x, int T, float *F_last, 
     return hipSuccess;
 }
 
+// The persistent loop of a small all-pulled problem (plan option): step size
+// and weight-update rate from the plan's device scalars.
+static hipError_t enqueue_iters_small(ffsat_plan *pl, float *x, int T, float *F, int32_t *n_sat, int32_t *U, bool erwa,
+                                      hipStream_t s)
+{
+    const PullLayout &P = pl->p->lay[IO_F32].pull[pl->persistent_class];
+    PullArgs a{};
+    a.x = x;
+    a.pptr = P.d_pptr;
+    a.pent = P.d_pent;
+    a.rk = P.d_rk;
+    a.eta_dev = pl->d_hyper;
+    a.n = pl->p->n;
+    a.B = pl->B;
+    return launch_iters_small(PULL_E[pl->persistent_class], a, pl->p->m, P.n_ent, T, F, n_sat, U, pl->p->d_w, erwa,
+                              pl->d_hyper + 1, s);
+}
+
 extern "C" ffsat_status ffsat_run_steps(ffsat_plan *pl, float *x, int32_t T, float eta, float *F_last, void *stream)
 {
     if (!pl || !x) return fail(FFSAT_E_INVALID_ARG, "NULL argument");
@@ -2142,6 +2179,11 @@ extern "C" ffsat_status ffsat_run_steps(ffsat_plan *pl, float *x, int32_t T, flo
     if ((st = check_finite<float>(pl, x, s)) != FFSAT_OK) return st;
     // the step size goes to device memory ahead of the (captured) steps
     HIPCHK(launch_set_f32x2(pl->d_hyper, eta, 0.f, s));
+    if (pl->persistent_class) {
+        // one launch: all T steps in one workgroup
+        HIPCHK(enqueue_iters_small(pl, x, T, F_last, nullptr, nullptr, false, s));
+        return FFSAT_OK;
+    }
     if (!pl->use_graphs) {
         HIPCHK(enqueue_steps(pl, x, T, F_last, s));
         return FFSAT_OK;
@@ -2246,6 +2288,11 @@ extern "C" ffsat_status ffsat_run_iters(ffsat_plan *pl, float *x, int32_t T, flo
     const bool erwa = alpha > 0.f;
     // step size and rate go to device memory ahead of the (captured) iterations
     HIPCHK(launch_set_f32x2(pl->d_hyper, eta, alpha, s));
+    if (pl->persistent_class) {
+        // one launch: all T iterations in one workgroup
+        HIPCHK(enqueue_iters_small(pl, x, T, F, n_sat, U, erwa, s));
+        return FFSAT_OK;
+    }
     auto body = [&](hipStream_t cs) {
         if (pl->iter_side) return enqueue_iters_overlapped(pl, x, T, erwa, F, n_sat, U, cs);
         return enqueue_iters(pl, x, T, erwa, F, n_sat, U, cs);

@@ -261,6 +261,8 @@ struct ffsat_plan {
     int pull = 0;
     bool pull_auto = false;
     int pull_vc = 8;                 // variables per wave of k_pull
+    bool persistent = false;         // ffsat_run_steps as one persistent launch (small all-pulled problems)
+    int persistent_class = 0;        // the pull class whose entry lists it reads (0: not eligible)
     float *d_xalt = nullptr;         // [n][B] second point buffer of in-place pulled steps
     std::string tune_log;            // [launch structure, pull length, ms per evaluation] per tuned candidate
     int64_t captures = 0;            // graphs captured over the plan's life
@@ -334,6 +336,41 @@ struct PullArgs {
 };
 constexpr int RK_TABLE = 40;
 hipError_t launch_pull(int E, const PullArgs &a, hipStream_t s);
+// Persistent loop of T fused iterations of a small problem whose constraints
+// are all pulled: one workgroup; x, the gradient, per-pair objective and
+// violation counts, the weights, U and the entry lists in LDS
+// (iters_small_lds bytes <= ITERS_SMALL_LDS).  Optional outputs of the last
+// iteration's point: F, n_sat, U; with erwa, the weight update after every
+// iteration.
+constexpr int ITERS_SMALL_LDS = 65536 - 512;   // leaves room for the kernel's own small arrays
+size_t iters_small_lds(int E, int n, int B, int m, int64_t n_ent);
+hipError_t launch_iters_small(int E, const PullArgs &a, int m, int64_t n_ent, int T, float *F, int32_t *n_sat,
+                              int32_t *U, float *w, bool erwa, const float *alpha_dev, hipStream_t s);
+
+// Maximum over a block of up to 1024 threads (values >= 0); every thread
+// gets it.  Uses red[16] and one barrier.
+__device__ __forceinline__ int32_t block_max_1024(int32_t v, int32_t *red)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    // every lane of every wave ends with the block maximum (counts are >= 0)
+    v = lane < (int)(blockDim.x >> 6) ? red[lane] : 0;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+// The adaptive weight of a constraint violated by u of the batch's restarts
+// (Prop. 3 with r = u / max U, r = 0 when nothing is violated); one
+// expression for every kernel that updates weights.
+__device__ __forceinline__ float erwa_weight(float w, int32_t u, int32_t umax, float inv, float alpha)
+{
+    const float r = umax > 0 ? (float)u * inv : 0.0f;
+    return (1.0f - alpha) * w + alpha * r;
+}
 hipError_t launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t launch_reduce_f64(const ReduceArgs<double> &r, hipStream_t s);
 // parts: 1 = gradient / step and level 1 of the sums, 2 = level 2, 3 = both
