@@ -16,9 +16,11 @@ objective are produced.
 
 `roofline` describes the kernel with the most time per step, timed live
 with HIP events on the stream it runs on.  One convention throughout:
-root-of-unity kernels do 10 k^2 FMA-class operations per (constraint,
-restart) (2 FLOP each) against the published vector peak of their
-arithmetic type (FP32 157.3, FP64 78.6 TFLOP/s); transform-free chains and
+root-of-unity kernels are priced at 10 k^2 FLOP per (constraint, restart)
+against the published vector peak of their arithmetic type (FP32 157.3,
+FP64 78.6 TFLOP/s) -- the kernels' own count, about 7 k^2 (14 FLOP per
+literal and complex frequency over floor(k/2) frequencies), is reported
+beside it as flop_exact_per_launch / frac_exact; transform-free chains and
 the reduction move 8 B per (literal, restart) in the evaluation (a gathered
 point, a slot written) plus 4 B per (literal, restart) and 8 B per
 (variable, restart) in the reduction; the pulled gradient moves 4 B per
@@ -52,7 +54,7 @@ UNIT = "literal-gradient evals/s"
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}     # published vector peaks
 CLOCK_GHZ, SIMDS = 2.4, 1024                  # 256 CUs x 4 SIMDs
-OPS_PER_K2 = 10.0                              # root-of-unity work per (constraint, restart)
+FLOP_PER_K2 = 10.0                             # root-of-unity work per (constraint, restart), in FLOP
 
 
 WORKLOADS = {
@@ -107,9 +109,17 @@ def parse():
 
 def bin_work(bd, B):
     """Algorithmic work of one evaluation bin per launch: (flop, bytes, dtype)."""
-    flop = 2.0 * OPS_PER_K2 * bd.get("k2_per_restart", 0.0) * B
+    flop = FLOP_PER_K2 * bd.get("k2_per_restart", 0.0) * B
     nbytes = 8.0 * bd["lits"] * B
     return flop, nbytes, bd["ct"]
+
+
+def bin_flop_exact(bd, B):
+    """The kernels' own FLOP count of a bin per launch: 14 per (literal,
+    complex frequency) over the floor(k/2) frequencies conjugate symmetry
+    leaves, 4 per frequency, 8 per literal of a real chain (about 7 k^2 per
+    root-of-unity constraint and restart)."""
+    return bd.get("flops_per_restart", 0.0) * B
 
 
 def bound_of(flop, nbytes, dt):
@@ -135,10 +145,10 @@ def roofline_entry(label, flop, nbytes, dt, avg_s, launches_per_step):
 
 def kernel_card(workload, kernel_name):
     """Counters of one kernel from the committed rocprofv3 summary
-    (profiles/<workload>_counters.txt, its `card:` lines), if the library
-    sources hash to the value recorded with them; else None."""
+    (profiles/eval_step_<workload>_counters.txt, its `card:` lines), if the
+    library sources hash to the value recorded with them; else None."""
     from paper_2308_15020_amd.profsum import kernel_source_hash
-    path = os.path.join(ROOT, "profiles", f"{workload}_counters.txt")
+    path = os.path.join(ROOT, "profiles", f"eval_step_{workload}_counters.txt")
     if not os.path.exists(path):
         return None
     for line in open(path):
@@ -228,6 +238,7 @@ def measure(name, args, dev, headline):
                      f"{sum(1 for b in grp if b['class'] == 'dft')} root-of-unity, "
                      f"{sum(b['count'] for b in grp)} constraints)")
             ent = roofline_entry(label, flop, nbytes, "f32", avg_s, per_step)
+            ent["flop_exact_per_launch"] = sum(bin_flop_exact(b, B) for b in grp)
             ent["kernel_name"] = "k_eval_group"
         elif k["bin"] >= 0:
             bd = bins[k["bin"]]
@@ -235,6 +246,7 @@ def measure(name, args, dev, headline):
             label = (f"eval bin {k['bin']} ({bd['class']}, {bd['ct']} arithmetic, seg {bd['seg']}, L {bd['L']}, "
                      f"{bd['count']} constraints, len <= {bd['maxk']})")
             ent = roofline_entry(label, flop, nbytes, dt, avg_s, per_step)
+            ent["flop_exact_per_launch"] = bin_flop_exact(bd, B)
             ent["kernel_name"] = (f"k_eval<float, {'double' if bd['ct'] == 'f64' else 'float'}, {bd['seg']}, "
                                   f"{bd['L']}, {'true' if bd['class'] == 'dft' else 'false'}>")
         elif k["bin"] == -3:
@@ -268,10 +280,12 @@ def measure(name, args, dev, headline):
         if m is None:
             merged[e["kernel_name"]] = dict(e, _t=e["avg_launch_ms"] * e["launches_per_step"], _f=e["flop_per_launch"]
                                             * e["launches_per_step"], _b=e["bytes_per_launch"] * e["launches_per_step"],
+                                            _x=e.get("flop_exact_per_launch", 0.0) * e["launches_per_step"],
                                             _n=e["launches_per_step"], parts=1)
         else:
             m["_t"] += e["avg_launch_ms"] * e["launches_per_step"]
             m["_f"] += e["flop_per_launch"] * e["launches_per_step"]
+            m["_x"] += e.get("flop_exact_per_launch", 0.0) * e["launches_per_step"]
             m["_b"] += e["bytes_per_launch"] * e["launches_per_step"]
             m["_n"] += e["launches_per_step"]
             m["parts"] += 1
@@ -282,6 +296,9 @@ def measure(name, args, dev, headline):
                              m["_f"] / n, m["_b"] / n, m["arith"], m["_t"] / n / 1e3, n)
         ent["kernel_name"] = kname
         ent["ms_per_step"] = m["_t"]
+        if m["_x"] > 0 and ent["bound"] == "alu":
+            ent["flop_exact_per_launch"] = m["_x"] / n
+            ent["frac_exact"] = m["_x"] / n / (m["_t"] / n / 1e3) / 1e12 / PEAK_TFLOPS[m["arith"]]
         kernels.append(ent)
     kernels.sort(key=lambda e: -e["ms_per_step"])
     dom = dict(kernels[0])
@@ -299,7 +316,8 @@ def measure(name, args, dev, headline):
             dom["valu_insts_per_launch"] = vi
             dom["valu_issue"] = vi * 4.0 / (SIMDS * CLOCK_GHZ * 1e9 * dom["avg_launch_ms"] / 1e3)
     for e in kernels:
-        for key in ("flop_per_launch", "bytes_per_launch", "achieved", "frac", "avg_launch_ms", "ms_per_step"):
+        for key in ("flop_per_launch", "flop_exact_per_launch", "bytes_per_launch", "achieved", "frac", "frac_exact",
+                    "avg_launch_ms", "ms_per_step"):
             if key in e and isinstance(e[key], float):
                 e[key] = float(f"{e[key]:.5g}")
     res = {"workload": wl["desc"].format(B=B), "n_vars": inst.n_vars, "n_cons": inst.m, "nnz": inst.nnz,

@@ -1440,11 +1440,43 @@ static ffsat_status set_pull(ffsat_plan *pl, int c)
     return FFSAT_OK;
 }
 
-// With MODE_AUTO (or an automatic pull choice), times one full FP32
-// evaluation with the fused step (on the tuner's scratch points, step size
-// 0, the stepped point written to the second buffer as in the step loops)
-// under each launch structure and pull class and keeps the fastest; the
-// choice is cached with the shapes.
+static hipError_t enqueue_iters(ffsat_plan *pl, float *x, int T, bool erwa, float *F, int32_t *n_sat, int32_t *U,
+                                hipStream_t s);
+static hipError_t enqueue_iters_overlapped(ffsat_plan *pl, float *x, int T, bool erwa, float *F,
+                                           int32_t *n_sat, int32_t *U, hipStream_t s);
+// Time of one fused iteration (objective, exact check, projected step) under
+// the plan's current launch structure and pull class, as the step loops run
+// it (side-stream overlap of consecutive iterations included): TUNE_ITERS
+// iterations on the tuner's scratch points with step size 0 from the plan's
+// device scalar and no weight update, enqueued eagerly (no graph) once to
+// warm up and then TUNE_REPS times under events.
+static ffsat_status time_iterations(ffsat_plan *pl, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float *ms)
+{
+    constexpr int TUNE_ITERS = 4, TUNE_REPS = 3;
+    if (!pl->d_tune_u) {
+        HIPCHK(hipMalloc(&pl->d_tune_u, sizeof(int32_t) * (size_t)pl->p->m));
+        pl->device_bytes += (int64_t)(sizeof(int32_t) * (size_t)pl->p->m);
+    }
+    HIPCHK(launch_set_f32x2(pl->d_hyper, 0.f, 0.f, s));
+    auto run = [&]() {
+        return pl->iter_side
+                   ? enqueue_iters_overlapped(pl, pl->d_scratch_x, TUNE_ITERS, false, nullptr, nullptr, pl->d_tune_u, s)
+                   : enqueue_iters(pl, pl->d_scratch_x, TUNE_ITERS, false, nullptr, nullptr, pl->d_tune_u, s);
+    };
+    HIPCHK(run());
+    HIPCHK(hipEventRecord(e0, s));
+    for (int r = 0; r < TUNE_REPS; ++r) HIPCHK(run());
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    *ms = t / (TUNE_REPS * TUNE_ITERS);
+    return FFSAT_OK;
+}
+
+// With MODE_AUTO (or an automatic pull choice), times the fused iteration
+// (time_iterations) under each launch structure and pull class and keeps the
+// fastest; the choice is cached with the shapes.
 static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cache, hipStream_t s)
 {
     if (!pl->mode_auto && !pl->pull_auto) return FFSAT_OK;
@@ -1476,9 +1508,8 @@ static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cach
                 const std::pair<int, int> cand{m, pl->pull};
                 if (std::find(cands.begin(), cands.end(), cand) == cands.end()) cands.push_back(cand);
             }
-        // two sweeps over the candidates (a warm-up evaluation, then three
-        // timed ones each); a candidate's time is its faster sweep, so that a
-        // slow moment of the device does not decide the choice
+        // two sweeps over the candidates; a candidate's time is its faster
+        // sweep, so that a slow moment of the device does not decide the choice
         std::vector<float> tbest(cands.size(), 1e30f);
         for (int sweep = 0; sweep < 2; ++sweep) {
             for (size_t i = 0; i < cands.size(); ++i) {
@@ -1487,22 +1518,9 @@ static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cach
                 ffsat_status st = set_pull(pl, cands[i].second);
                 if (st != FFSAT_OK) return st;
                 if ((st = build_groups(pl)) != FFSAT_OK) return st;
-                float *out = pl->pull ? pl->d_xalt : nullptr;
-                if ((st = run_eval<float>(pl, pl->d_scratch_x, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                          true, pl->d_scratch_x, 0.f, s, nullptr, nullptr, out)) != FFSAT_OK)
-                    return st;
-                HIPCHK(hipEventRecord(e0, s));
-                const int reps = 3;
-                for (int r = 0; r < reps; ++r)
-                    if ((st = run_eval<float>(pl, pl->d_scratch_x, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                              nullptr, true, pl->d_scratch_x, 0.f, s, nullptr, nullptr, out)) !=
-                        FFSAT_OK)
-                        return st;
-                HIPCHK(hipEventRecord(e1, s));
-                HIPCHK(hipEventSynchronize(e1));
                 float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                tbest[i] = std::min(tbest[i], ms / reps);
+                if ((st = time_iterations(pl, s, e0, e1, &ms)) != FFSAT_OK) return st;
+                tbest[i] = std::min(tbest[i], ms);
             }
         }
         // the fastest; an earlier candidate keeps the choice within 2 %
@@ -1752,6 +1770,7 @@ extern "C" ffsat_status ffsat_plan_destroy(ffsat_plan *pl)
     clear_graphs(pl);
     (void)hipFree(pl->d_hyper);
     (void)hipFree(pl->d_xalt);
+    (void)hipFree(pl->d_tune_u);
     (void)hipFree(pl->d_gent);
     (void)hipFree(pl->d_gblk);
     for (int io = 0; io < 2; ++io) {
