@@ -303,10 +303,12 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
     // FP64 bounded-basis frequencies over several lanes: whole product by a
     // butterfly, then a division (no scans)
     constexpr bool ALLRED = sizeof(CT) == 8 && L >= 2 && FORM != 3;
-    // FP64 form-1 factors of short segments: the reverse pass reuses the
-    // forward pass's tau * l (2 more VGPRs per position, one FP64 multiply
-    // less per position and frequency)
-    constexpr bool KEEP_U = sizeof(CT) == 8 && FORM == 1 && SEG <= 16;
+    // FP64 form-1 factors in 32-lane groups (segments of at most 16): the
+    // reverse pass reuses the forward pass's tau * l (2 more VGPRs per
+    // position, one FP64 multiply less per position and frequency); these
+    // kernels run at 2 waves per SIMD either way, narrower groups would drop
+    // from 3 to 2
+    constexpr bool KEEP_U = sizeof(CT) == 8 && FORM == 1 && SEG <= 16 && L == 32;
     (void)j;
     const CT tk = fr.tk;
     CT pr[SEG], pi[SEG];

@@ -66,6 +66,15 @@ def test_autograd_weighted_objective(ffs):
     got = gx[vv.ravel(), bb.ravel()] / gFn[bb.ravel()]
     scale = var_scale(inst)[vv.ravel()]
     assert np.max(np.abs(got - fd) / scale) <= 1e-5
+    # the GPU's own weight gradient over the first 64 restarts (gF zeroed
+    # beyond them) against FP64 central differences of the oracle's F in w
+    gF64 = gF.clone()
+    gF64[64:] = 0.0
+    x2 = torch.from_numpy(xn).to(DEV).requires_grad_(True)
+    w2 = torch.from_numpy(inst.weights.copy()).to(DEV).requires_grad_(True)
+    (objective(x2, w2, plan) * gF64).sum().backward()
+    gw64_gpu = w2.grad.cpu().numpy()
+    nat = np.abs(gFn[:64]).sum()
     cs = rng.integers(0, inst.m, 64)
     for c in cs:
         e = np.zeros(inst.m)
@@ -73,9 +82,7 @@ def test_autograd_weighted_objective(ffs):
         Fp = oracle.eval_batch(inst, xn.astype(np.float64)[:, :64], w=inst.weights + e, want_g=False)["F"]
         Fm = oracle.eval_batch(inst, xn.astype(np.float64)[:, :64], w=inst.weights - e, want_g=False)["F"]
         fdw = gFn[:64] @ (Fp - Fm) / 2e-6
-        # the GPU weight gradient restricted to the first 64 restarts
-        gw64 = float(gFn[:64] @ full["con_val"][c, :64])
-        assert abs(fdw - gw64) <= 1e-6 * np.abs(gFn[:64]).sum()
+        assert abs(fdw - float(gw64_gpu[c])) <= TOL32 * nat, (c, fdw, gw64_gpu[c])
 
 
 def _splitmix64(z):

@@ -6,7 +6,8 @@
   restarts against the oracle, in the launch shapes the benchmark uses, and
   one fused iteration through the benchmark's own graph-replayed path;
 * large mixed n=100000 (420000 3-SAT, 10000 XOR, 2000 at-least-t of length
-  128..512), 256 restarts: sampled restarts against the oracle.
+  128..512), 256 restarts: sampled restarts against the oracle, and one fused
+  iteration through the benchmark's own autotuned, graph-replayed path.
 """
 import numpy as np
 import pytest
@@ -108,6 +109,37 @@ def test_mixed_n2000_b1024_fused_iteration_bench_path(ffs):
     assert np.max(np.abs(x1[:, cols] - want_x1) / (eta * S)) <= TOL32 + 1e-6
     want_w1 = oracle.erwa(chk["U"], w0, alpha)
     assert np.max(np.abs(w1 - want_w1)) <= 1e-6
+
+
+def test_large_n100000_b256_fused_iteration_bench_path(ffs):
+    """The large instance in the benchmark's configuration (autotuned plan:
+    launch structure and pull class as the bench picks them, FP64 bins past
+    256 literals, graph-replayed fused iteration with check, projected step
+    and ERWA): F and the stepped point on sampled restarts against the
+    oracle, satisfied counts and U over all 256 restarts bit-exact, the new
+    weights against the oracle's update."""
+    from gpu_cases import var_scale
+    inst = workloads.config3(workloads.instance_seed(3, 0))
+    B, eta, alpha = 256, 0.05, 0.4
+    prob = ffs.Problem(inst, device=0)
+    plan = ffs.Plan(prob, B, autotune=True)
+    print(plan.describe()["mode"], plan.describe()["pull"])
+    x0 = workloads.points(inst.n_vars, B, workloads.point_seed(workloads.instance_seed(3, 0)))
+    xt = torch.from_numpy(x0).to(DEV)
+    w0 = np.ones(inst.m)
+    prob.set_weights(w0.astype(np.float32))
+    out = to_np(plan.run_iters(xt, 1, eta, alpha))
+    x1 = xt.cpu().numpy()
+    w1 = prob.get_weights().cpu().numpy()
+    cols = np.array([0, 131, 255])
+    ref = oracle.eval_batch(inst, np.ascontiguousarray(x0[:, cols].astype(np.float64)), want_g=True)
+    assert np.max(np.abs(out["F"][cols] - ref["F"])) / float(inst.m) <= TOL32
+    chk = oracle.check(inst, x0.astype(np.float64))
+    assert np.array_equal(out["n_sat"], chk["n_sat"]) and np.array_equal(out["U"], chk["U"])
+    want_x1 = np.clip(x0[:, cols].astype(np.float64) - eta * ref["g"], -1.0, 1.0)
+    S = var_scale(inst)[:, None]
+    assert np.max(np.abs(x1[:, cols] - want_x1) / (eta * S)) <= TOL32 + 1e-6
+    assert np.max(np.abs(w1 - oracle.erwa(chk["U"], w0, alpha))) <= 1e-6
 
 
 def test_large_mixed_n100000_b256_sampled(ffs):
