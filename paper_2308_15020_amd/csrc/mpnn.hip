@@ -2,11 +2,13 @@
 // points over the clause-variable incidence graph (3 rounds of messages,
 // hidden width H, BF16 matrix-core products with FP32 accumulation).
 //
-//  * k_gemm: C = op(A) op(B) on the matrix cores (v_mfma_f32_32x32x8 bf16):
-//    one wave per 32x32 tile of C, operands read as FP32 and rounded to
-//    bfloat16 (round to nearest even) on load, FP32 accumulators; optional
-//    split of the reduction dimension into fixed slices (summed in a fixed
-//    order afterwards), bias + ReLU epilogue.
+//  * k_gemm: C = op(A) op(B) on the matrix cores (gfx950's
+//    v_mfma_f32_32x32x16 bf16, 16 reduction terms per instruction): one
+//    wave per 32x32 tile of C, operands read as FP32 (two 16-byte loads per
+//    lane where the reduction dimension is contiguous and aligned) and
+//    rounded to bfloat16 (round to nearest even) in registers, FP32
+//    accumulators; optional split of the reduction dimension into fixed
+//    slices (summed in a fixed order afterwards), bias + ReLU epilogue.
 //  * k_gather: per-row weighted sums over the incidence (both directions),
 //    used for the messages and for their transposes in the backward pass.
 //  * head (tanh of a dot product), loss, column sums, Adam, proposals.
@@ -14,7 +16,8 @@
 
 namespace ffsat {
 
-typedef short __attribute__((ext_vector_type(4))) bf16x4_t;
+typedef short __attribute__((ext_vector_type(8))) s16x8_t;
+typedef __bf16 __attribute__((ext_vector_type(8))) bf16x8_t;
 typedef float __attribute__((ext_vector_type(16))) f32x16_t;
 
 __device__ __forceinline__ short to_bf16(float f)
@@ -24,17 +27,45 @@ __device__ __forceinline__ short to_bf16(float f)
     return (short)(u >> 16);
 }
 
+// The 8 values of a lane's share of one 16-term block: p[0..7] when the
+// block lies inside [.., lim) and contiguous rows may be read as two
+// aligned 16-byte loads (vec), else element by element with stride st,
+// zero past lim.
+__device__ __forceinline__ s16x8_t load8_bf16(const float *p, size_t st, int k, int lim, bool ok, bool vec)
+{
+    float v[8];
+    if (ok && vec && k + 8 <= lim) {
+        const float4 x0 = *reinterpret_cast<const float4 *>(p);
+        const float4 x1 = *reinterpret_cast<const float4 *>(p + 4);
+        v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
+        v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = (ok && k + q < lim) ? p[(size_t)q * st] : 0.f;
+    }
+    s16x8_t r;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r[q] = to_bf16(v[q]);
+    return r;
+}
+
 // C[M][N] (ldc) = sum over k in this block's slice of opA[i][k] * opB[k][j]
 //   opA[i][k] = TA ? A[k*lda + i] : A[i*lda + k]
 //   opB[k][j] = TB ? B[j*ldb + k] : B[k*ldb + j]
 // EPI 0: C (+ slice * slice_stride) = acc; EPI 1: C = relu(acc + bias[j]).
-// Lane layout of the 32x32x8 instruction (one block): lane l supplies
-// A[l % 32][4*(l/32) + v] and B[4*(l/32) + v][l % 32], v = 0..3, and holds
-// D[8*(q/4) + 4*(l/32) + q%4][l % 32], q = 0..15.
+// One 32x32x16 instruction per 16 reduction terms: lane l supplies the 8
+// terms k0 + 8*(l/32) + v (v = 0..7) of row l % 32 of opA and of column
+// l % 32 of opB (the same k for both operands, so the sum covers the block
+// whatever order the unit takes them in), and holds
+// D[8*(q/4) + 4*(l/32) + q%4][l % 32], q = 0..15.  vec_a / vec_b: the
+// contiguous operand (opA rows for !TA, opB columns for TB) may be read as
+// 16-byte loads (base 16-byte aligned, leading dimension a multiple of 4;
+// slices and blocks start at multiples of 16).
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(64) void k_gemm(int M, int N, int K, const float *__restrict__ A, int lda,
                                              const float *__restrict__ B, int ldb, float *C, int ldc,
-                                             const float *__restrict__ bias, int kslice, size_t slice_stride)
+                                             const float *__restrict__ bias, int kslice, size_t slice_stride,
+                                             int vec_a, int vec_b)
 {
     const int l = threadIdx.x;
     const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
@@ -42,24 +73,19 @@ __global__ __launch_bounds__(64) void k_gemm(int M, int N, int K, const float *_
     const int ke = min(K, kb + kslice);
     const int ai = i0 + (l & 31);
     const int bj = j0 + (l & 31);
-    const int kq = 4 * (l >> 5);
+    const int kh = 8 * (l >> 5);
+    const bool aok = ai < M, bok = bj < N;
     f32x16_t acc;
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = 0.f;
-    for (int k0 = kb; k0 < ke; k0 += 8) {
-        bf16x4_t a, b;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int k = k0 + kq + v;
-            float av = 0.f, bv = 0.f;
-            if (k < ke) {
-                if (ai < M) av = TA ? A[(size_t)k * lda + ai] : A[(size_t)ai * lda + k];
-                if (bj < N) bv = TB ? B[(size_t)bj * ldb + k] : B[(size_t)k * ldb + bj];
-            }
-            a[v] = to_bf16(av);
-            b[v] = to_bf16(bv);
-        }
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+        const int k = k0 + kh;
+        const s16x8_t a = TA ? load8_bf16(A + (size_t)k * lda + ai, (size_t)lda, k, ke, aok, false)
+                             : load8_bf16(A + (size_t)ai * lda + k, 1, k, ke, aok, vec_a != 0);
+        const s16x8_t b = TB ? load8_bf16(B + (size_t)bj * ldb + k, 1, k, ke, bok, vec_b != 0)
+                             : load8_bf16(B + (size_t)k * ldb + bj, (size_t)ldb, k, ke, bok, false);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                      acc, 0, 0, 0);
     }
     const int j = j0 + (l & 31);
     if (j >= N) return;
@@ -82,14 +108,16 @@ hipError_t gemm(bool ta, bool tb, int epi, int M, int N, int K, const float *A, 
     if (M <= 0 || N <= 0) return hipSuccess;
     splits = splits < 1 ? 1 : splits;
     int kslice = (K + splits - 1) / splits;
-    kslice = ((kslice + 7) / 8) * 8;
+    kslice = ((kslice + 15) / 16) * 16;   // whole 16-term blocks per slice
     splits = (K + kslice - 1) / kslice;
     if (splits < 1) splits = 1;
     dim3 grid((M + 31) / 32, (N + 31) / 32, epi == 0 ? splits : 1);
-    if (epi == 1) kslice = ((K + 7) / 8) * 8;
+    if (epi == 1) kslice = ((K + 15) / 16) * 16;
+    const int vec_a = !ta && ((uintptr_t)A % 16 == 0) && lda % 4 == 0;
+    const int vec_b = tb && ((uintptr_t)B % 16 == 0) && ldb % 4 == 0;
 #define LAUNCH(TA, TB, E)                                                                                   \
     hipLaunchKernelGGL((k_gemm<TA, TB, E>), grid, dim3(64), 0, s, M, N, K, A, lda, B, ldb, C, ldc, bias, kslice, \
-                       slice_stride)
+                       slice_stride, vec_a, vec_b)
     if (epi == 0) {
         if (!ta && !tb) LAUNCH(false, false, 0);
         else if (!ta && tb) LAUNCH(false, true, 0);
