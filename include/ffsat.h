@@ -130,13 +130,14 @@ typedef struct {
                                 (0 = 8); reserved[4] = 1: ffsat_run_steps and
                                 ffsat_run_iters run all T iterations in one
                                 persistent launch of one workgroup (points,
-                                gradients, weights, counts and the per-variable
-                                constraint lists in LDS) when every constraint is
-                                transform-free of length <= 7 and 16 n B + 8 m +
-                                4 (n + 1) + 4 E e <= 65024 bytes (e literal
-                                occurrences, E = 4 if every constraint has at
-                                most 3 literals, else 8), else as usual; others
-                                must be 0 */
+                                per-occurrence gradient terms, constraint values,
+                                weights, counts and the per-variable constraint
+                                lists in LDS) when every constraint is
+                                transform-free of length <= 7 and 8 n B + 4 e B +
+                                4 m B + 8 m + 4 B + 4 (n + 1) + 4 e + 4 E e <=
+                                65024 bytes (e literal occurrences, E = 4 if
+                                every constraint has at most 3 literals, else 8),
+                                else as usual; others must be 0 */
 } ffsat_plan_opts;
 
 /* ---- errors ------------------------------------------------------------- */

@@ -1691,14 +1691,14 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
     if (st == FFSAT_OK && !pl->pull_auto) st = set_pull(pl, preq == 1 ? PULL_OFF : (preq == 2 ? PULL_LE7 : PULL_LE3));
     if (st == FFSAT_OK && pl->persistent) {
         // eligible: every constraint pulled (transform-free, length <= 7) and
-        // x and the gradient of all (variable, restart) pairs fit in LDS
+        // the points, the per-pair gradient terms and the lists fit in LDS
         int cmin = PULL_LE3;
         bool all = !pl->bins[IO_F32].empty();
         for (const Bin &b : pl->bins[IO_F32]) {
             all = all && b.pk >= PULL_LE7;
             cmin = std::min(cmin, b.pk);
         }
-        if (all && (int64_t)16 * p->n * B + (int64_t)8 * p->m <= ITERS_SMALL_LDS) {
+        if (all && (int64_t)8 * p->n * B + (int64_t)4 * p->m * B + (int64_t)8 * p->m <= ITERS_SMALL_LDS) {
             st = build_pull(p, cmin);
             if (st == FFSAT_OK &&
                 iters_small_lds(PULL_E[cmin], p->n, B, p->m, p->lay[IO_F32].pull[cmin].n_ent) <= ITERS_SMALL_LDS)

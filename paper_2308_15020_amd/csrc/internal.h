@@ -338,8 +338,8 @@ struct PullArgs {
 constexpr int RK_TABLE = 40;
 hipError_t launch_pull(int E, const PullArgs &a, hipStream_t s);
 // Persistent loop of T fused iterations of a small problem whose constraints
-// are all pulled: one workgroup; x, the gradient, per-pair objective and
-// violation counts, the weights, U and the entry lists in LDS
+// are all pulled: one workgroup; x, the per-(entry, restart) gradient terms,
+// the constraint values, the weights, U and the entry lists in LDS
 // (iters_small_lds bytes <= ITERS_SMALL_LDS).  Optional outputs of the last
 // iteration's point: F, n_sat, U; with erwa, the weight update after every
 // iteration.

@@ -244,14 +244,20 @@ hipError_t launch_pull(int E, const PullArgs &a, hipStream_t s)
 // Persistent loop of T fused iterations (App. A.3, Alg. 5; with the exact
 // check of Alg. 1 and the weight update of Prop. 3) of a small problem whose
 // constraints are all pulled (short transform-free chains): one workgroup
-// holds every (variable, restart) pair's point, gradient, objective term and
-// violation count, the weights, the violation counts U and the entry lists
-// in LDS and runs all T iterations in one launch.  Per iteration: every thread forms the
-// gradient of its pairs from their entry lists (terms in list order, FP64
-// sums) and, at the entries of first literals, the objective terms and the
-// exact check (U by LDS integer atomics, order-free); a barrier; the step;
-// then, with erwa, the maximum of U, the weight update and U cleared.  The
-// last iteration's F and n_sat are sums over the variables in order.
+// holds the points, the weights, the violation counts U and the entry lists
+// in LDS and runs all T iterations in one launch.  Per iteration:
+//  1. one thread per (entry, restart) pair forms the entry's gradient term
+//     (the weighted leave-one-out product of its constraint) and, at the
+//     entries of first literals, the constraint's value and the exact check
+//     (U and the restart's violation count by LDS integer atomics, which
+//     are order-free);
+//  2. one thread per (variable, restart) pair adds its entries' terms in
+//     list order in FP64, rounds to FP32 as the evaluation does, and takes
+//     the projected step in place;
+//  3. with erwa, the maximum of U and the weight update; U cleared.
+// The last iteration's F is summed per variable over its first-literal
+// entries in list order (FP32), then over the variables in order (FP64):
+// every result equals that of a thread walking each pair's list alone.
 template <int E>
 __global__ __launch_bounds__(1024) void k_iters_small(PullArgs a, int m, int T, float *F, int32_t *n_sat,
                                                       int32_t *Uout, float *wg, int erwa,
@@ -264,16 +270,20 @@ __global__ __launch_bounds__(1024) void k_iters_small(PullArgs a, int m, int T, 
     extern __shared__ float sm[];
     __shared__ int32_t red[16];
     __shared__ float rkt[RK_TABLE];
-    const int nB = a.n * a.B;
+    const int B = a.B;
+    const int nB = a.n * B;
     const int n_ent = pptr_g[a.n];
-    float *xs = sm;                                   // [n][B] points
-    float *gs = xs + nB;                              // [n][B] gradients
-    float *fs = gs + nB;                              // [n][B] objective terms of owned constraints
-    int32_t *cs = reinterpret_cast<int32_t *>(fs + nB);   // [n][B] violated owned constraints
-    float *ws = reinterpret_cast<float *>(cs + nB);       // [m] weights
-    int32_t *us = reinterpret_cast<int32_t *>(ws + m);    // [m] violations per constraint
-    int32_t *pptr = us + m;                               // [n + 1] entry bounds
-    int32_t *pent = pptr + a.n + 1;                       // [n_ent][E] entries
+    const int eB = n_ent * B;
+    float *xs = sm;                                           // [n][B] points
+    float *fv = xs + nB;                                      // [n][B] objective sums of owned constraints
+    float *tg = fv + nB;                                      // [n_ent][B] gradient terms
+    float *fe = tg + eB;                                      // [m][B] constraint values
+    float *ws = fe + (size_t)m * B;                           // [m] weights
+    int32_t *us = reinterpret_cast<int32_t *>(ws + m);        // [m] violations per constraint
+    int32_t *nu = us + m;                                     // [B] violated constraints per restart
+    int32_t *pptr = nu + B;                                   // [n + 1] entry bounds
+    int32_t *own = pptr + a.n + 1;                            // [n_ent] owning variable
+    int32_t *pent = own + n_ent;                              // [n_ent][E] entries
     float *xg = const_cast<float *>(a.x);
     const bool check = n_sat != nullptr || Uout != nullptr || erwa;
     for (int i = threadIdx.x; i < nB; i += blockDim.x) xs[i] = xg[i];
@@ -281,79 +291,95 @@ __global__ __launch_bounds__(1024) void k_iters_small(PullArgs a, int m, int T, 
         ws[c] = wg[c];
         us[c] = 0;
     }
+    for (int b = threadIdx.x; b < B; b += blockDim.x) nu[b] = 0;
     for (int i = threadIdx.x; i <= a.n; i += blockDim.x) pptr[i] = pptr_g[i];
     for (int i = threadIdx.x; i < n_ent * E; i += blockDim.x) pent[i] = pent_g[i];
     for (int i = threadIdx.x; i < RK_TABLE; i += blockDim.x) rkt[i] = rkt_g[i];
+    for (int v = threadIdx.x; v < a.n; v += blockDim.x)
+        for (int p = pptr_g[v]; p < pptr_g[v + 1]; ++p) own[p] = v;
     __syncthreads();
     const float eta = a.eta_dev != nullptr ? *a.eta_dev : a.eta;
     const float alpha = alpha_dev != nullptr ? *alpha_dev : 0.f;
 #pragma unroll 1
     for (int it = 0; it < T; ++it) {
-        for (int i = threadIdx.x; i < nB; i += blockDim.x) {
-            const int v = i / a.B, b = i - v * a.B;
-            double acc = 0.0;
-            float facc = 0.f;
-            int nuns = 0;
-            const float xv = xs[i];
-            const int p0 = pptr[v], p1 = pptr[v + 1];
-            for (int p = p0; p < p1; ++p) {
-                const int32_t *en = pent + (size_t)p * E;
-                const int orig = en[0], meta = en[1];
-                const int rk = meta & 7, km1 = (meta >> 3) & 7;
-                const bool own_neg = (meta >> 10) & 1;
-                const float al = rkt[rk], be = rkt[8 + rk];
-                float prod = 1.f;
-                int cnt = 0;
+        // 1. entry terms at x_t
+        for (int i = threadIdx.x; i < eB; i += blockDim.x) {
+            const int p = i / B, b = i - p * B;
+            const int32_t *en = pent + (size_t)p * E;
+            const int orig = en[0], meta = en[1];
+            const int rk = meta & 7, km1 = (meta >> 3) & 7;
+            const bool own_neg = (meta >> 10) & 1;
+            const float al = rkt[rk], be = rkt[8 + rk];
+            float prod = 1.f;
+            int cnt = 0;
 #pragma unroll
-                for (int t = 0; t < NO; ++t) {
-                    if (t < km1) {
-                        const int o = en[2 + t];
-                        const float xo = xs[(o & 0x7fffffff) * a.B + b];
-                        prod *= __builtin_fmaf(be, o < 0 ? -xo : xo, al);
-                        cnt += ((o < 0) != (xo < 0.f)) ? 1 : 0;
-                    }
+            for (int t = 0; t < NO; ++t) {
+                if (t < km1) {
+                    const int o = en[2 + t];
+                    const float xo = xs[(o & 0x7fffffff) * B + b];
+                    prod *= __builtin_fmaf(be, o < 0 ? -xo : xo, al);
+                    cnt += ((o < 0) != (xo < 0.f)) ? 1 : 0;
                 }
-                const float wc = ws[orig];
-                const float gterm = wc * (rkt[24 + rk] * prod);
-                acc += (double)(own_neg ? -gterm : gterm);
-                if ((meta >> 11) & 1) {
-                    const float lown = own_neg ? -xv : xv;
-                    const float we = __builtin_fmaf(rkt[16 + rk], prod * __builtin_fmaf(be, lown, al), rkt[32 + rk]);
-                    facc = __builtin_fmaf(wc, we, facc);
-                    if (check) {
-                        cnt += (own_neg != (xv < 0.f)) ? 1 : 0;
-                        const int chk = ((meta >> 6) & 15) - 2;
-                        const bool sat = chk >= 0 ? (cnt >= chk) : ((cnt & 1) == (chk == -2 ? 1 : 0));
-                        if (!sat) {
-                            ++nuns;
-                            atomicAdd(&us[orig], 1);
-                        }
+            }
+            const float gterm = ws[orig] * (rkt[24 + rk] * prod);
+            tg[i] = own_neg ? -gterm : gterm;
+            if ((meta >> 11) & 1) {
+                const float xv = xs[own[p] * B + b];
+                const float lown = own_neg ? -xv : xv;
+                fe[(size_t)orig * B + b] = __builtin_fmaf(rkt[16 + rk], prod * __builtin_fmaf(be, lown, al), rkt[32 + rk]);
+                if (check) {
+                    cnt += (own_neg != (xv < 0.f)) ? 1 : 0;
+                    const int chk = ((meta >> 6) & 15) - 2;
+                    const bool sat = chk >= 0 ? (cnt >= chk) : ((cnt & 1) == (chk == -2 ? 1 : 0));
+                    if (!sat) {
+                        atomicAdd(&us[orig], 1);
+                        atomicAdd(&nu[b], 1);
                     }
                 }
             }
-            gs[i] = (float)acc;   // same rounding as the evaluation's gradient
-            fs[i] = facc;
-            cs[i] = nuns;
         }
         __syncthreads();
+        // 2. ordered sums and the step; the last iteration's objective sums
+        const bool last = it == T - 1;
         for (int i = threadIdx.x; i < nB; i += blockDim.x) {
-            const float y = __builtin_fmaf(-eta, gs[i], xs[i]);
+            const int v = i / B, b = i - v * B;
+            const int p0 = pptr[v], p1 = pptr[v + 1];
+            double acc = 0.0;
+            int p = p0;
+            for (; p + 4 <= p1; p += 4) {
+                const float t0 = tg[(p + 0) * B + b], t1 = tg[(p + 1) * B + b];
+                const float t2 = tg[(p + 2) * B + b], t3 = tg[(p + 3) * B + b];
+                acc += (double)t0;
+                acc += (double)t1;
+                acc += (double)t2;
+                acc += (double)t3;
+            }
+            for (; p < p1; ++p) acc += (double)tg[p * B + b];
+            if (last) {
+                float facc = 0.f;
+                for (int q = p0; q < p1; ++q) {
+                    const int32_t *en = pent + (size_t)q * E;
+                    if ((en[1] >> 11) & 1) facc = __builtin_fmaf(ws[en[0]], fe[(size_t)en[0] * B + b], facc);
+                }
+                fv[i] = facc;
+            }
+            const float g = (float)acc;   // same rounding as the evaluation's gradient
+            const float y = __builtin_fmaf(-eta, g, xs[i]);
             xs[i] = fminf(fmaxf(y, -1.0f), 1.0f);
         }
-        if (it == T - 1) {
-            for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
+        if (last) {
+            __syncthreads();
+            for (int b = threadIdx.x; b < B; b += blockDim.x) {
                 double f = 0.0;
-                int u = 0;
-                for (int v = 0; v < a.n; ++v) {
-                    f += (double)fs[v * a.B + b];
-                    u += cs[v * a.B + b];
-                }
+                for (int v = 0; v < a.n; ++v) f += (double)fv[v * B + b];
                 if (F != nullptr) F[b] = (float)f;
-                if (n_sat != nullptr) n_sat[b] = m - u;
+                if (n_sat != nullptr) n_sat[b] = m - nu[b];
             }
             if (Uout != nullptr)
                 for (int c = threadIdx.x; c < m; c += blockDim.x) Uout[c] = us[c];
         }
+        // 3. weights (the counts are complete since the barrier after 1.;
+        // the weights were last read in 2.)
         if (erwa) {
             int32_t mx = 0;
             for (int c = threadIdx.x; c < m; c += blockDim.x) mx = max(mx, us[c]);
@@ -361,9 +387,11 @@ __global__ __launch_bounds__(1024) void k_iters_small(PullArgs a, int m, int T, 
             const float inv = umax > 0 ? 1.0f / (float)umax : 0.0f;
             for (int c = threadIdx.x; c < m; c += blockDim.x) ws[c] = erwa_weight(ws[c], us[c], umax, inv, alpha);
         }
-        __syncthreads();   // every U read before it is cleared; the step and weights before the next gradient
-        if (check)
+        __syncthreads();   // every count read before it is cleared; the step and weights before the next terms
+        if (check) {
             for (int c = threadIdx.x; c < m; c += blockDim.x) us[c] = 0;
+            for (int b = threadIdx.x; b < B; b += blockDim.x) nu[b] = 0;
+        }
         __syncthreads();
     }
     for (int i = threadIdx.x; i < nB; i += blockDim.x) xg[i] = xs[i];
@@ -373,17 +401,18 @@ __global__ __launch_bounds__(1024) void k_iters_small(PullArgs a, int m, int T, 
 
 size_t iters_small_lds(int E, int n, int B, int m, int64_t n_ent)
 {
-    return (size_t)16 * n * B + (size_t)8 * m + (size_t)4 * (n + 1) + (size_t)4 * E * n_ent;
+    return (size_t)8 * n * B + (size_t)4 * n_ent * B + (size_t)4 * m * B + (size_t)8 * m + (size_t)4 * B +
+           (size_t)4 * (n + 1) + (size_t)4 * n_ent + (size_t)4 * E * n_ent;
 }
 
 hipError_t launch_iters_small(int E, const PullArgs &a, int m, int64_t n_ent, int T, float *F, int32_t *n_sat,
                               int32_t *U, float *w, bool erwa, const float *alpha_dev, hipStream_t s)
 {
     if (T <= 0) return hipSuccess;
-    const int64_t nB = (int64_t)a.n * a.B;
+    const int64_t work = std::max<int64_t>(std::max<int64_t>(n_ent * a.B, (int64_t)a.n * a.B), m);
     const size_t lds = iters_small_lds(E, a.n, a.B, m, n_ent);
     if (lds > (size_t)ITERS_SMALL_LDS) return hipErrorInvalidValue;
-    const int threads = nB >= 1024 ? 1024 : (int)((nB + 63) / 64) * 64;
+    const int threads = work >= 1024 ? 1024 : (int)((work + 63) / 64) * 64;
     if (E == 4)
         hipLaunchKernelGGL((k_iters_small<4>), dim3(1), dim3(threads), lds, s, a, m, T, F, n_sat, U, w, erwa ? 1 : 0,
                            alpha_dev, a.rk, a.pent, a.pptr);

@@ -6,7 +6,7 @@ against the usual launch sequence (needs an MI355X).
 * random 3-SAT n = 50, m = 213, one restart, 200 iterations: at every
   iteration the oracle evaluates the GPU's own iterate (F, the next point,
   n_sat and U bit-exact);
-* random 3-SAT n = 100 with 8 restarts: T iterations with adaptive weights
+* random 3-SAT n = 100 with 4 restarts: T iterations with adaptive weights
   against the same iterations of a plan without the persistent loop;
 * a problem with long constraints: the option falls back to the usual steps.
 """
@@ -57,7 +57,7 @@ def test_persistent_3sat_trajectory(ffs):
 @pytest.mark.parametrize("T", [1, 7])
 def test_persistent_matches_usual_iterations(ffs, T):
     inst = workloads.random_hybrid(100, 5, n_or=426, or_len=(3, 3))
-    B, eta, alpha = 8, 0.05, 0.4
+    B, eta, alpha = 4, 0.05, 0.4
     x0 = torch.from_numpy(workloads.points(inst.n_vars, B, 6)).to(DEV)
     res = {}
     for persistent in (False, True):
