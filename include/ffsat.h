@@ -115,7 +115,8 @@ typedef struct {
     int32_t reserved[8];     /* reserved[0] = 1: launch all bins on the caller's stream
                                 (no internal side streams); reserved[1]: launch
                                 structure of the FP32 evaluation, 0 automatic (the
-                                autotuner times the others and keeps the fastest),
+                                autotuner times the others and keeps the fastest;
+                                without it 2, or 3 when reserved[2] is 2 or 3),
                                 1 one launch per bin, 2 one grouped launch for all
                                 bins, 3 a grouped launch for the root-of-unity bins
                                 with the others beside it; reserved[2]: gradient of

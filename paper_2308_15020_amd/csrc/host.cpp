@@ -1652,9 +1652,13 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
         return fail(FFSAT_E_INVALID_ARG, "reserved[1] (evaluation mode) must be in 0..3");
     }
     pl->mode_auto = req == MODE_AUTO;
-    pl->mode = pl->mode_auto ? MODE_GROUP_DFT : req;   // the tuner may change an automatic choice
-    pl->grouped = pl->mode != MODE_PER_BIN;
     const int preq = opts ? opts->reserved[2] : 0;
+    // an automatic choice before (or without) the tuner: one grouped launch
+    // of every bin, fewest launches per step; the root-of-unity group with the
+    // transform-free bins beside it when the pulled gradient is asked for,
+    // which the all-bin group excludes
+    pl->mode = !pl->mode_auto ? req : (preq == 2 || preq == 3 ? MODE_GROUP_DFT : MODE_GROUP_ALL);
+    pl->grouped = pl->mode != MODE_PER_BIN;
     const int vc = opts ? opts->reserved[3] : 0;
     const int persist = opts ? opts->reserved[4] : 0;
     if (preq < 0 || preq > 3 || vc < 0 || vc > PULL_VC_MAX || persist < 0 || persist > 1 ||
