@@ -31,7 +31,9 @@ same kernel (VALU instructions, HBM bytes) come from the committed rocprofv3
 summary in profiles/ while the kernel sources are unchanged.
 
 Secondary workloads measured in the same run: the mixed n = 2000 instance
-(1024 restarts) and the 3-SAT part of the large instance alone.  The time
+(1024 restarts), the 3-SAT part of the large instance alone, and random
+3-SAT n = 50 with one restart in the persistent one-workgroup loop (a
+latency line: its `roofline` names the loop and claims no fraction).  The time
 to solve with learned against uniform initialisation (the metric's second
 half) follows.  `cpu_baseline`: the FP64 oracle on the host cores, on a
 leading subset of the headline's restarts.
@@ -315,6 +317,12 @@ def measure(name, args, dev, headline):
             # wave64 VALU instructions issue one per 4 cycles per SIMD
             dom["valu_insts_per_launch"] = vi
             dom["valu_issue"] = vi * 4.0 / (SIMDS * CLOCK_GHZ * 1e9 * dom["avg_launch_ms"] / 1e3)
+    if wl.get("persistent") and desc.get("persistent_steps"):
+        # the timed loop runs in the persistent kernel, not in the eager
+        # loop's kernels listed under `kernels`: a latency line
+        dom = {"kernel": "persistent fused-iteration loop (one workgroup runs every iteration of a replay)",
+               "kernel_name": "k_iters_small", "bound": "latency", "achieved": None, "peak": None, "unit": None,
+               "frac": None, "traffic": None, "us_per_iteration": ms_per_step * 1e3}
     for e in kernels:
         for key in ("flop_per_launch", "flop_exact_per_launch", "bytes_per_launch", "achieved", "frac", "frac_exact",
                     "avg_launch_ms", "ms_per_step"):
@@ -489,7 +497,7 @@ def main():
     print(f"[bench] {args.workload}: {head['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     secondary = {}
     if not args.no_secondary:
-        for name in ("mixed2000", "large3sat"):
+        for name in ("mixed2000", "large3sat", "uf50"):
             if name == args.workload:
                 continue
             r, _, _ = measure(name, args, dev, False)
