@@ -1038,7 +1038,9 @@ static std::map<std::string, Shape> read_cache(const std::string &path)
     std::stringstream ss;
     ss << f.rdbuf();
     const std::string s = ss.str();
-    // entries: "key": [cpw, wpb, fg] (fg optional, default 1)
+    // entries: "key": [cpw, wpb, fg] (fg optional, default 1); the launch
+    // structure entries ("|mode|" keys) hold [structure, pull class,
+    // grouped chain cpw] instead
     size_t i = 0;
     while ((i = s.find('"', i)) != std::string::npos) {
         const size_t j = s.find('"', i + 1);
@@ -1048,8 +1050,13 @@ static std::map<std::string, Shape> read_cache(const std::string &path)
         if (lb == std::string::npos || rb == std::string::npos) break;
         int cpw = 0, wpb = 0, fg = 1;
         const int got = sscanf(s.c_str() + lb + 1, "%d , %d , %d", &cpw, &wpb, &fg);
-        if (got >= 2 && cpw > 0 && wpb > 0 && (got == 2 || (fg == 1 || fg == 2 || fg == 4)))
+        if (key.find("|mode|") != std::string::npos) {
+            if (got == 3 && cpw >= MODE_PER_BIN && cpw <= MODE_GROUP_DFT && wpb >= PULL_OFF && wpb <= PULL_LE3 &&
+                fg >= 0 && fg <= 64)
+                out[key] = {cpw, wpb, fg};
+        } else if (got >= 2 && cpw > 0 && wpb > 0 && (got == 2 || (fg == 1 || fg == 2 || fg == 4))) {
             out[key] = {cpw, wpb, got == 3 ? fg : 1};
+        }
         i = rb + 1;
     }
     return out;
@@ -1354,6 +1361,40 @@ static std::vector<Bin> split_bins(const std::vector<Bin> &in, const std::vector
     return out;
 }
 
+// Longest run of constraints one wave takes in a transform-free bin.
+static int real_cpw_cap(const Bin &b) { return b.maxk <= 8 ? 16 : (b.maxk <= 32 ? 8 : 2); }
+
+// Constraints per wave of the transform-free bins that run inside the
+// all-bin grouped launch.  There they share the chip with the root-of-unity
+// blocks, and short waves cost more than in a launch of their own: timed in
+// the grouped launch, 8 per wave beat both the per-bin choice (1-2, timed
+// alone) and 4 or 16 on the mixed instances at B = 256 and 1024.
+constexpr int GROUP_REAL_CPW = 8;
+static bool real_in_all_group(const Bin &b)
+{
+    return b.cls == CLASS_REAL && !b.uc && group_variant(b.ct, b.cls, b.seg, b.L) >= 0;
+}
+// Sets (c > 0) or restores (c == 0) those bins' constraints per wave; the
+// objective rows follow.  c > 0 only for MODE_GROUP_ALL plans.  While no
+// group value is set the bins hold their per-bin shapes, which are recorded
+// when one is set.
+static void set_group_real_cpw(ffsat_plan *pl, int c)
+{
+    std::vector<Bin> &bins = pl->bins[IO_F32];
+    if (c == pl->group_real_cpw) return;
+    if (pl->group_real_cpw == 0) {
+        pl->solo_real_cpw.resize(bins.size());
+        for (size_t i = 0; i < bins.size(); ++i) pl->solo_real_cpw[i] = bins[i].cpw;
+    }
+    for (size_t i = 0; i < bins.size(); ++i) {
+        Bin &b = bins[i];
+        if (!real_in_all_group(b)) continue;
+        b.cpw = c > 0 ? std::max(1, std::min({c, real_cpw_cap(b), b.count})) : pl->solo_real_cpw[i];
+    }
+    pl->group_real_cpw = c;
+    pl->fpart_rows[IO_F32] = fpart_rows_of(bins);
+}
+
 // Constraints per wave: enough waves per bin to cover the chip (the
 // autotuner refines this).  Root-of-unity bins keep one constraint per wave.
 static void default_shapes(ffsat_plan *pl)
@@ -1376,7 +1417,7 @@ static void default_shapes(ffsat_plan *pl)
                 }
                 continue;
             }
-            const int cap = b.maxk <= 8 ? 16 : (b.maxk <= 32 ? 8 : 2);
+            const int cap = real_cpw_cap(b);
             const int64_t n_rb = (pl->B + (64 / b.L) - 1) / (64 / b.L);
             const int64_t target = 4096;   // waves
             int64_t cpw = ((int64_t)b.count * n_rb) / target;
@@ -1384,6 +1425,8 @@ static void default_shapes(ffsat_plan *pl)
         }
         pl->fpart_rows[io] = fpart_rows_of(pl->bins[io]);
     }
+    pl->group_real_cpw = 0;
+    if (pl->mode == MODE_GROUP_ALL) set_group_real_cpw(pl, GROUP_REAL_CPW);
 }
 
 // Destroys every cached executable graph, each after its latest launch has
@@ -1479,17 +1522,20 @@ static ffsat_status time_iterations(ffsat_plan *pl, hipStream_t s, hipEvent_t e0
 // fastest; the choice is cached with the shapes.
 static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cache, hipStream_t s)
 {
-    if (!pl->mode_auto && !pl->pull_auto) return FFSAT_OK;
+    // a fixed structure and pull class leave nothing to time, except the
+    // transform-free bins' constraints per wave inside the all-bin group
+    if (!pl->mode_auto && !pl->pull_auto && pl->mode != MODE_GROUP_ALL) return FFSAT_OK;
     char kb[200];
     snprintf(kb, sizeof kb, "gfx950|mode|B%d|n%d|m%d|nnz%lld|bins%zu|%s%d", pl->B, pl->p->n, pl->p->m,
              (long long)pl->p->nnz, pl->bins[IO_F32].size(), pl->mode_auto ? "a" : "f", pl->mode);
     const std::string key = pl->pull_auto ? std::string(kb) + "|pull" : std::string(kb) + "|p" + std::to_string(pl->pull);
     auto hit = cache.find(key);
-    int best_mode = pl->mode, best_pull = pl->pull;
+    int best_mode = pl->mode, best_pull = pl->pull, best_gc = 0;
     if (hit != cache.end() && hit->second.cpw >= MODE_PER_BIN && hit->second.cpw <= MODE_GROUP_DFT &&
-        hit->second.wpb >= PULL_OFF && hit->second.wpb <= PULL_LE3) {
+        hit->second.wpb >= PULL_OFF && hit->second.wpb <= PULL_LE3 && hit->second.fg >= 0 && hit->second.fg <= 64) {
         best_mode = hit->second.cpw;
         best_pull = hit->second.wpb;
+        best_gc = best_mode == MODE_GROUP_ALL ? hit->second.fg : 0;
     } else {
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
@@ -1498,24 +1544,34 @@ static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cach
                                                : std::vector<int>{pl->mode};
         std::vector<int> pulls = pl->pull_auto ? std::vector<int>{PULL_OFF, PULL_LE3, PULL_LE7}
                                                : std::vector<int>{pl->pull};
-        // distinct (launch structure, pull class) candidates after normalisation
-        std::vector<std::pair<int, int>> cands;
+        // distinct (launch structure, pull class, grouped chain cpw)
+        // candidates after normalisation; the all-bin group is timed with
+        // its transform-free bins at 4, 8 and 16 constraints per wave (the
+        // per-bin shapes, timed alone, do not carry over into the group)
+        struct Cand {
+            int mode, pull, gc;
+            bool operator==(const Cand &o) const { return mode == o.mode && pull == o.pull && gc == o.gc; }
+        };
+        std::vector<Cand> cands;
         for (int m : modes)
             for (int c : pulls) {
                 pl->mode = m;
                 ffsat_status st = set_pull(pl, c);
                 if (st != FFSAT_OK) return st;
-                const std::pair<int, int> cand{m, pl->pull};
-                if (std::find(cands.begin(), cands.end(), cand) == cands.end()) cands.push_back(cand);
+                for (int gc : m == MODE_GROUP_ALL ? std::vector<int>{GROUP_REAL_CPW, 4, 16} : std::vector<int>{0}) {
+                    const Cand cand{m, pl->pull, gc};
+                    if (std::find(cands.begin(), cands.end(), cand) == cands.end()) cands.push_back(cand);
+                }
             }
         // two sweeps over the candidates; a candidate's time is its faster
         // sweep, so that a slow moment of the device does not decide the choice
         std::vector<float> tbest(cands.size(), 1e30f);
         for (int sweep = 0; sweep < 2; ++sweep) {
             for (size_t i = 0; i < cands.size(); ++i) {
-                pl->mode = cands[i].first;
+                pl->mode = cands[i].mode;
                 pl->grouped = pl->mode != MODE_PER_BIN;
-                ffsat_status st = set_pull(pl, cands[i].second);
+                set_group_real_cpw(pl, cands[i].gc);
+                ffsat_status st = set_pull(pl, cands[i].pull);
                 if (st != FFSAT_OK) return st;
                 if ((st = build_groups(pl)) != FFSAT_OK) return st;
                 float ms = 0.f;
@@ -1527,18 +1583,23 @@ static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cach
         size_t bi = 0;
         for (size_t i = 1; i < cands.size(); ++i)
             if (tbest[i] < tbest[bi] * 0.98f) bi = i;
-        best_mode = cands[bi].first;
-        best_pull = cands[bi].second;
+        best_mode = cands[bi].mode;
+        best_pull = cands[bi].pull;
+        best_gc = cands[bi].gc;
         std::ostringstream lg;
         for (size_t i = 0; i < cands.size(); ++i)
-            lg << (i ? ", " : "") << "[" << cands[i].first << ", " << PULL_K[cands[i].second] << ", " << tbest[i] << "]";
+            lg << (i ? ", " : "") << "[" << cands[i].mode << ", " << PULL_K[cands[i].pull] << ", " << cands[i].gc
+               << ", " << tbest[i] << "]";
         pl->tune_log = lg.str();
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        cache[key] = Shape{best_mode, best_pull, 1};   // mode in the cpw field, pull class in wpb
+        // mode in the cpw field, pull class in wpb, grouped chain cpw in fg
+        cache[key] = Shape{best_mode, best_pull, best_gc};
     }
     pl->mode = best_mode;
     pl->grouped = best_mode != MODE_PER_BIN;
+    set_group_real_cpw(pl, best_mode == MODE_GROUP_ALL ? best_gc : 0);
+    clear_graphs(pl);
     return set_pull(pl, best_pull);
 }
 
@@ -1563,6 +1624,7 @@ extern "C" ffsat_status ffsat_plan_tune(ffsat_plan *pl, void *stream)
     a.want_check = 1;
     const Layout &Ly = p->lay[IO_F32];
     bool dirty = false;
+    set_group_real_cpw(pl, 0);   // per-bin shapes are timed bin by bin
     for (Bin &b : pl->bins[IO_F32]) {
         const std::string key = bin_key(pl, b, IO_F32);
         auto hit = cache.find(key);
@@ -1827,7 +1889,7 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
       << ", \"pull_other_slots\": " << (pl->pull ? pl->p->lay[IO_F32].pull[pl->pull].n_rest : 0)
       << ", \"pull_chunks\": " << (pl->pull ? (pl->p->n + pl->pull_vc - 1) / pl->pull_vc : 0)
       << ", \"objective_rows\": " << eval_rows(pl, IO_F32, pl->pull)
-      << ", \"tuned_modes\": [" << pl->tune_log << "], \"persistent_steps\": "
+      << ", \"group_real_cpw\": " << pl->group_real_cpw << ", \"tuned_modes\": [" << pl->tune_log << "], \"persistent_steps\": "
       << (pl->persistent_class ? "true" : "false") << ", \"bins\": {";
     for (int io = 0; io < 2; ++io) {
         o << (io ? ", " : "") << "\"" << (io ? "f64" : "f32") << "\": [";

@@ -376,7 +376,10 @@ def test_autotune_keeps_results(ffs, mixed, tmp_path):
     assert np.max(np.abs(a["con_val"] - b["con_val"])) <= TOL32
     assert np.max(np.abs(a["F"] - b["F"])) <= 1e-6 * np.abs(inst.weights).sum()
     p2 = ffs.Plan(prob, B, autotune=True, tune_cache=cache)     # served from the cache file
-    assert p2.describe()["bins"] == d["bins"]
+    d2 = p2.describe()
+    assert d2["tuned_modes"] == []     # launch structure and pull class read back, not timed again
+    assert d2["bins"] == d["bins"]
+    assert (d2["mode"], d2["pull"], d2["group_real_cpw"]) == (d["mode"], d["pull"], d["group_real_cpw"])
 
 
 def test_debug_nonfinite(ffs):
