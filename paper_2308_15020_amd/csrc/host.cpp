@@ -1040,7 +1040,7 @@ static std::map<std::string, Shape> read_cache(const std::string &path)
     const std::string s = ss.str();
     // entries: "key": [cpw, wpb, fg] (fg optional, default 1); the launch
     // structure entries ("|mode|" keys) hold [structure, pull class,
-    // grouped chain cpw] instead
+    // grouped shapes coded as 8 * chain cpw + frequency split] instead
     size_t i = 0;
     while ((i = s.find('"', i)) != std::string::npos) {
         const size_t j = s.find('"', i + 1);
@@ -1052,7 +1052,7 @@ static std::map<std::string, Shape> read_cache(const std::string &path)
         const int got = sscanf(s.c_str() + lb + 1, "%d , %d , %d", &cpw, &wpb, &fg);
         if (key.find("|mode|") != std::string::npos) {
             if (got == 3 && cpw >= MODE_PER_BIN && cpw <= MODE_GROUP_DFT && wpb >= PULL_OFF && wpb <= PULL_LE3 &&
-                fg >= 0 && fg <= 64)
+                fg >= 0 && fg <= 8 * 64 + 7)
                 out[key] = {cpw, wpb, fg};
         } else if (got >= 2 && cpw > 0 && wpb > 0 && (got == 2 || (fg == 1 || fg == 2 || fg == 4))) {
             out[key] = {cpw, wpb, got == 3 ? fg : 1};
@@ -1364,34 +1364,48 @@ static std::vector<Bin> split_bins(const std::vector<Bin> &in, const std::vector
 // Longest run of constraints one wave takes in a transform-free bin.
 static int real_cpw_cap(const Bin &b) { return b.maxk <= 8 ? 16 : (b.maxk <= 32 ? 8 : 2); }
 
-// Constraints per wave of the transform-free bins that run inside the
-// all-bin grouped launch.  There they share the chip with the root-of-unity
-// blocks, and short waves cost more than in a launch of their own: timed in
-// the grouped launch, 8 per wave beat both the per-bin choice (1-2, timed
-// alone) and 4 or 16 on the mixed instances at B = 256 and 1024.
+// Shapes of the bins inside a grouped launch.  There they share the chip
+// with each other, and short waves cost more than in a launch of their own,
+// so the per-bin shapes (timed bin by bin, they favour 1-2 transform-free
+// constraints per wave and split long root-of-unity constraints' frequencies
+// over 4 waves) do not carry over.  Timed in the grouped launch on the mixed
+// instances at B = 256 and 1024: 8 constraints per wave beat 1-2, 4 and 16,
+// and one wave per root-of-unity unit beat 4.
 constexpr int GROUP_REAL_CPW = 8;
-static bool real_in_all_group(const Bin &b)
+constexpr int GROUP_DFT_FG = 1;
+constexpr int GROUP_CODE_MAX = 8 * 64 + 7;   // cache code of the grouped shapes: 8 * chain cpw + fg
+static bool in_group(const ffsat_plan *pl, const Bin &b)
 {
-    return b.cls == CLASS_REAL && !b.uc && group_variant(b.ct, b.cls, b.seg, b.L) >= 0;
+    if (b.uc || group_variant(b.ct, b.cls, b.seg, b.L) < 0) return false;
+    return b.cls == CLASS_DFT || pl->mode == MODE_GROUP_ALL;
 }
-// Sets (c > 0) or restores (c == 0) those bins' constraints per wave; the
-// objective rows follow.  c > 0 only for MODE_GROUP_ALL plans.  While no
+// Sets the group values (c: transform-free constraints per wave, all-bin
+// group only; f: root-of-unity frequency split, 1 or 4) or, with 0, gives
+// those bins back their per-bin shapes; the objective rows follow.  While no
 // group value is set the bins hold their per-bin shapes, which are recorded
 // when one is set.
-static void set_group_real_cpw(ffsat_plan *pl, int c)
+static void set_group_shapes(ffsat_plan *pl, int c, int f)
 {
     std::vector<Bin> &bins = pl->bins[IO_F32];
-    if (c == pl->group_real_cpw) return;
-    if (pl->group_real_cpw == 0) {
-        pl->solo_real_cpw.resize(bins.size());
-        for (size_t i = 0; i < bins.size(); ++i) pl->solo_real_cpw[i] = bins[i].cpw;
+    if (c == pl->group_real_cpw && f == pl->group_dft_fg) return;
+    if (pl->group_real_cpw == 0 && pl->group_dft_fg == 0) {
+        pl->solo_cpw.resize(bins.size());
+        pl->solo_fg.resize(bins.size());
+        for (size_t i = 0; i < bins.size(); ++i) {
+            pl->solo_cpw[i] = bins[i].cpw;
+            pl->solo_fg[i] = bins[i].fg;
+        }
     }
     for (size_t i = 0; i < bins.size(); ++i) {
         Bin &b = bins[i];
-        if (!real_in_all_group(b)) continue;
-        b.cpw = c > 0 ? std::max(1, std::min({c, real_cpw_cap(b), b.count})) : pl->solo_real_cpw[i];
+        const bool g = pl->grouped && in_group(pl, b);
+        if (b.cls == CLASS_REAL)
+            b.cpw = g && c > 0 ? std::max(1, std::min({c, real_cpw_cap(b), b.count})) : pl->solo_cpw[i];
+        else
+            b.fg = g && f > 0 ? f : pl->solo_fg[i];
     }
     pl->group_real_cpw = c;
+    pl->group_dft_fg = f;
     pl->fpart_rows[IO_F32] = fpart_rows_of(bins);
 }
 
@@ -1426,7 +1440,8 @@ static void default_shapes(ffsat_plan *pl)
         pl->fpart_rows[io] = fpart_rows_of(pl->bins[io]);
     }
     pl->group_real_cpw = 0;
-    if (pl->mode == MODE_GROUP_ALL) set_group_real_cpw(pl, GROUP_REAL_CPW);
+    pl->group_dft_fg = 0;
+    if (pl->grouped) set_group_shapes(pl, pl->mode == MODE_GROUP_ALL ? GROUP_REAL_CPW : 0, GROUP_DFT_FG);
 }
 
 // Destroys every cached executable graph, each after its latest launch has
@@ -1522,20 +1537,22 @@ static ffsat_status time_iterations(ffsat_plan *pl, hipStream_t s, hipEvent_t e0
 // fastest; the choice is cached with the shapes.
 static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cache, hipStream_t s)
 {
-    // a fixed structure and pull class leave nothing to time, except the
-    // transform-free bins' constraints per wave inside the all-bin group
-    if (!pl->mode_auto && !pl->pull_auto && pl->mode != MODE_GROUP_ALL) return FFSAT_OK;
+    // a fixed structure and pull class leave nothing to time but the shapes
+    // inside a grouped launch
+    if (!pl->mode_auto && !pl->pull_auto && pl->mode == MODE_PER_BIN) return FFSAT_OK;
     char kb[200];
     snprintf(kb, sizeof kb, "gfx950|mode|B%d|n%d|m%d|nnz%lld|bins%zu|%s%d", pl->B, pl->p->n, pl->p->m,
              (long long)pl->p->nnz, pl->bins[IO_F32].size(), pl->mode_auto ? "a" : "f", pl->mode);
     const std::string key = pl->pull_auto ? std::string(kb) + "|pull" : std::string(kb) + "|p" + std::to_string(pl->pull);
     auto hit = cache.find(key);
-    int best_mode = pl->mode, best_pull = pl->pull, best_gc = 0;
+    int best_mode = pl->mode, best_pull = pl->pull, best_gc = 0, best_gf = 0;
     if (hit != cache.end() && hit->second.cpw >= MODE_PER_BIN && hit->second.cpw <= MODE_GROUP_DFT &&
-        hit->second.wpb >= PULL_OFF && hit->second.wpb <= PULL_LE3 && hit->second.fg >= 0 && hit->second.fg <= 64) {
+        hit->second.wpb >= PULL_OFF && hit->second.wpb <= PULL_LE3 && hit->second.fg >= 0 &&
+        hit->second.fg <= GROUP_CODE_MAX) {
         best_mode = hit->second.cpw;
         best_pull = hit->second.wpb;
-        best_gc = best_mode == MODE_GROUP_ALL ? hit->second.fg : 0;
+        best_gc = best_mode == MODE_GROUP_ALL ? hit->second.fg / 8 : 0;
+        best_gf = best_mode != MODE_PER_BIN ? hit->second.fg % 8 : 0;
     } else {
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
@@ -1544,13 +1561,17 @@ static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cach
                                                : std::vector<int>{pl->mode};
         std::vector<int> pulls = pl->pull_auto ? std::vector<int>{PULL_OFF, PULL_LE3, PULL_LE7}
                                                : std::vector<int>{pl->pull};
-        // distinct (launch structure, pull class, grouped chain cpw)
-        // candidates after normalisation; the all-bin group is timed with
-        // its transform-free bins at 4, 8 and 16 constraints per wave (the
-        // per-bin shapes, timed alone, do not carry over into the group)
+        // distinct (launch structure, pull class, grouped shapes) candidates
+        // after normalisation; grouped launches are timed with their own
+        // shapes (the per-bin shapes, timed alone, do not carry over): the
+        // root-of-unity frequency split 1 or 4, and in the all-bin group the
+        // transform-free bins at 4, 8 or 16 constraints per wave
         struct Cand {
-            int mode, pull, gc;
-            bool operator==(const Cand &o) const { return mode == o.mode && pull == o.pull && gc == o.gc; }
+            int mode, pull, gc, gf;
+            bool operator==(const Cand &o) const
+            {
+                return mode == o.mode && pull == o.pull && gc == o.gc && gf == o.gf;
+            }
         };
         std::vector<Cand> cands;
         for (int m : modes)
@@ -1558,8 +1579,15 @@ static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cach
                 pl->mode = m;
                 ffsat_status st = set_pull(pl, c);
                 if (st != FFSAT_OK) return st;
-                for (int gc : m == MODE_GROUP_ALL ? std::vector<int>{GROUP_REAL_CPW, 4, 16} : std::vector<int>{0}) {
-                    const Cand cand{m, pl->pull, gc};
+                std::vector<std::pair<int, int>> shapes;
+                if (m == MODE_GROUP_ALL)
+                    shapes = {{GROUP_REAL_CPW, GROUP_DFT_FG}, {4, 1}, {16, 1}, {GROUP_REAL_CPW, 4}};
+                else if (m == MODE_GROUP_DFT)
+                    shapes = {{0, GROUP_DFT_FG}, {0, 4}};
+                else
+                    shapes = {{0, 0}};
+                for (const auto &sh : shapes) {
+                    const Cand cand{m, pl->pull, sh.first, sh.second};
                     if (std::find(cands.begin(), cands.end(), cand) == cands.end()) cands.push_back(cand);
                 }
             }
@@ -1570,7 +1598,7 @@ static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cach
             for (size_t i = 0; i < cands.size(); ++i) {
                 pl->mode = cands[i].mode;
                 pl->grouped = pl->mode != MODE_PER_BIN;
-                set_group_real_cpw(pl, cands[i].gc);
+                set_group_shapes(pl, cands[i].gc, cands[i].gf);
                 ffsat_status st = set_pull(pl, cands[i].pull);
                 if (st != FFSAT_OK) return st;
                 if ((st = build_groups(pl)) != FFSAT_OK) return st;
@@ -1586,19 +1614,21 @@ static ffsat_status tune_mode(ffsat_plan *pl, std::map<std::string, Shape> &cach
         best_mode = cands[bi].mode;
         best_pull = cands[bi].pull;
         best_gc = cands[bi].gc;
+        best_gf = cands[bi].gf;
         std::ostringstream lg;
         for (size_t i = 0; i < cands.size(); ++i)
             lg << (i ? ", " : "") << "[" << cands[i].mode << ", " << PULL_K[cands[i].pull] << ", " << cands[i].gc
-               << ", " << tbest[i] << "]";
+               << ", " << cands[i].gf << ", " << tbest[i] << "]";
         pl->tune_log = lg.str();
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        // mode in the cpw field, pull class in wpb, grouped chain cpw in fg
-        cache[key] = Shape{best_mode, best_pull, best_gc};
+        // structure in the cpw field, pull class in wpb, grouped shapes
+        // (8 * chain cpw + frequency split) in fg
+        cache[key] = Shape{best_mode, best_pull, 8 * best_gc + best_gf};
     }
     pl->mode = best_mode;
     pl->grouped = best_mode != MODE_PER_BIN;
-    set_group_real_cpw(pl, best_mode == MODE_GROUP_ALL ? best_gc : 0);
+    set_group_shapes(pl, best_gc, best_gf);
     clear_graphs(pl);
     return set_pull(pl, best_pull);
 }
@@ -1624,7 +1654,7 @@ extern "C" ffsat_status ffsat_plan_tune(ffsat_plan *pl, void *stream)
     a.want_check = 1;
     const Layout &Ly = p->lay[IO_F32];
     bool dirty = false;
-    set_group_real_cpw(pl, 0);   // per-bin shapes are timed bin by bin
+    set_group_shapes(pl, 0, 0);   // per-bin shapes are timed bin by bin
     for (Bin &b : pl->bins[IO_F32]) {
         const std::string key = bin_key(pl, b, IO_F32);
         auto hit = cache.find(key);
@@ -1889,7 +1919,8 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
       << ", \"pull_other_slots\": " << (pl->pull ? pl->p->lay[IO_F32].pull[pl->pull].n_rest : 0)
       << ", \"pull_chunks\": " << (pl->pull ? (pl->p->n + pl->pull_vc - 1) / pl->pull_vc : 0)
       << ", \"objective_rows\": " << eval_rows(pl, IO_F32, pl->pull)
-      << ", \"group_real_cpw\": " << pl->group_real_cpw << ", \"tuned_modes\": [" << pl->tune_log << "], \"persistent_steps\": "
+      << ", \"group_real_cpw\": " << pl->group_real_cpw << ", \"group_dft_fg\": " << pl->group_dft_fg
+      << ", \"tuned_modes\": [" << pl->tune_log << "], \"persistent_steps\": "
       << (pl->persistent_class ? "true" : "false") << ", \"bins\": {";
     for (int io = 0; io < 2; ++io) {
         o << (io ? ", " : "") << "\"" << (io ? "f64" : "f32") << "\": [";

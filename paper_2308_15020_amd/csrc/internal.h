@@ -264,10 +264,14 @@ struct ffsat_plan {
     bool persistent = false;         // ffsat_run_steps as one persistent launch (small all-pulled problems)
     int persistent_class = 0;        // the pull class whose entry lists it reads (0: not eligible)
     float *d_xalt = nullptr;         // [n][B] second point buffer of in-place pulled steps
-    std::string tune_log;            // [launch structure, pull length, grouped chain cpw, ms per fused iteration]
-    int group_real_cpw = 0;          // constraints per wave of the transform-free bins inside the all-bin group
-                                     // (0: their own per-bin shapes)
-    std::vector<int> solo_real_cpw;  // those bins' per-bin shapes, restored when they leave the group
+    std::string tune_log;            // [launch structure, pull length, grouped chain cpw, grouped fg,
+                                     //  ms per fused iteration] per tuned candidate
+    // shapes of the bins inside a grouped launch, timed there (0: the bins'
+    // own per-bin shapes): constraints per wave of the transform-free bins
+    // (all-bin group only) and the frequency split of the root-of-unity bins
+    int group_real_cpw = 0;
+    int group_dft_fg = 0;
+    std::vector<int> solo_cpw, solo_fg;   // the per-bin shapes, restored when the group values are cleared
     int32_t *d_tune_u = nullptr;     // [m] violation counts of the tuner's timed iterations
     int64_t captures = 0;            // graphs captured over the plan's life
     int64_t device_bytes = 0;

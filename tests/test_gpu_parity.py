@@ -379,7 +379,8 @@ def test_autotune_keeps_results(ffs, mixed, tmp_path):
     d2 = p2.describe()
     assert d2["tuned_modes"] == []     # launch structure and pull class read back, not timed again
     assert d2["bins"] == d["bins"]
-    assert (d2["mode"], d2["pull"], d2["group_real_cpw"]) == (d["mode"], d["pull"], d["group_real_cpw"])
+    keys = ("mode", "pull", "group_real_cpw", "group_dft_fg")
+    assert [d2[k] for k in keys] == [d[k] for k in keys]
 
 
 def test_debug_nonfinite(ffs):
