@@ -2,7 +2,8 @@
 //  * segmented reduction of per-literal slots into the gradient over the
 //    variable-major transpose (fixed order, deterministic), optionally
 //    fused with the projected step (App. A.3, Alg. 5: clip to [-1,1]);
-//  * two-level deterministic sum of objective partials (Def. 3);
+//  * two-level deterministic sum of objective partials (Def. 3), the second
+//    level over 16 waves per block of 64 restarts;
 //  * projected step; rounding of the variables (Alg. 1); adaptive weights
 //    (Prop. 3); weight gradient; small utilities.  The exact constraint
 //    check runs inside the evaluation kernels.
@@ -74,24 +75,46 @@ __global__ __launch_bounds__(RED_BLOCK) void k_reduce(ReduceArgs<IO> a, int n_gr
     }
 }
 
+// Level 2: a block per 64 restarts (lane = restart); its FSUM_WAVES waves
+// each add a contiguous share of the splits in order, then wave 0 adds the
+// waves' partials in wave order (a fixed order: deterministic).
+static constexpr int FSUM_WAVES = 16;
 template <typename IO>
-__global__ __launch_bounds__(64) void k_fsum2(ReduceArgs<IO> a, int splits)
+__global__ __launch_bounds__(64 * FSUM_WAVES) void k_fsum2(ReduceArgs<IO> a, int splits)
 {
-    const int b = blockIdx.x * 64 + threadIdx.x;
-    if (b >= a.B) return;
-    if (a.skip != nullptr && *a.skip == 0) return;
-    if (a.F != nullptr) {
-        double acc = 0.0;
+    __shared__ double fp[FSUM_WAVES][64];
+    __shared__ int cp[FSUM_WAVES][64];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int b = blockIdx.x * 64 + lane;
+    if (a.skip != nullptr && *a.skip == 0) return;   // uniform: the whole block leaves
+    const bool ok = b < a.B;
+    const int s0 = (int)(((int64_t)splits * w) / FSUM_WAVES), s1 = (int)(((int64_t)splits * (w + 1)) / FSUM_WAVES);
+    double facc = 0.0;
+    int cacc = 0;
+    if (ok) {
+        if (a.F != nullptr) {
 #pragma unroll 8
-        for (int s = 0; s < splits; ++s) acc += (double)a.ftmp[(size_t)s * a.B + b];
-        a.F[b] = (IO)acc;
-    }
-    if (a.n_sat != nullptr) {
-        int acc = 0;
+            for (int q = s0; q < s1; ++q) facc += (double)a.ftmp[(size_t)q * a.B + b];
+        }
+        if (a.n_sat != nullptr) {
 #pragma unroll 8
-        for (int s = 0; s < splits; ++s) acc += a.ctmp[(size_t)s * a.B + b];
-        a.n_sat[b] = a.m - acc;
+            for (int q = s0; q < s1; ++q) cacc += a.ctmp[(size_t)q * a.B + b];
+        }
     }
+    fp[w][lane] = facc;
+    cp[w][lane] = cacc;
+    __syncthreads();
+    if (w != 0 || !ok) return;
+    double f = 0.0;
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < FSUM_WAVES; ++q) {
+        f += fp[q][lane];
+        c += cp[q][lane];
+    }
+    if (a.F != nullptr) a.F[b] = (IO)f;
+    if (a.n_sat != nullptr) a.n_sat[b] = a.m - c;
 }
 
 // parts: 1 = gradient (and step) with level 1 of the sums, 2 = level 2 of
@@ -111,7 +134,7 @@ static hipError_t reduce_impl(const ReduceArgs<IO> &a, hipStream_t s, int parts 
         if (e != hipSuccess) return e;
     }
     if ((parts & 2) && rows) {
-        hipLaunchKernelGGL((k_fsum2<IO>), dim3((a.B + 63) / 64), dim3(64), 0, s, a, splits);
+        hipLaunchKernelGGL((k_fsum2<IO>), dim3((a.B + 63) / 64), dim3(64 * FSUM_WAVES), 0, s, a, splits);
         return hipGetLastError();
     }
     return hipSuccess;
