@@ -102,15 +102,27 @@ __global__ __launch_bounds__(64) void k_gemm(int M, int N, int K, const float *_
     }
 }
 
+// Reduction terms per slice when K is split `splits` ways: whole 16-term
+// blocks of the matrix-core instruction.
+static int gemm_kslice(int K, int splits)
+{
+    splits = splits < 1 ? 1 : splits;
+    const int kslice = (K + splits - 1) / splits;
+    return std::max(16, ((kslice + 15) / 16) * 16);
+}
+
+int gemm_slices(int K, int splits)
+{
+    const int kslice = gemm_kslice(K, splits);
+    return std::max(1, (K + kslice - 1) / kslice);
+}
+
 hipError_t gemm(bool ta, bool tb, int epi, int M, int N, int K, const float *A, int lda, const float *B, int ldb,
                 float *C, int ldc, const float *bias, int splits, size_t slice_stride, hipStream_t s)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
-    splits = splits < 1 ? 1 : splits;
-    int kslice = (K + splits - 1) / splits;
-    kslice = ((kslice + 15) / 16) * 16;   // whole 16-term blocks per slice
-    splits = (K + kslice - 1) / kslice;
-    if (splits < 1) splits = 1;
+    int kslice = gemm_kslice(K, splits);
+    splits = gemm_slices(K, splits);
     dim3 grid((M + 31) / 32, (N + 31) / 32, epi == 0 ? splits : 1);
     if (epi == 1) kslice = ((K + 15) / 16) * 16;
     const int vec_a = !ta && ((uintptr_t)A % 16 == 0) && lda % 4 == 0;
@@ -155,35 +167,80 @@ hipError_t sum_slices(int64_t len, int S, const float *part, size_t stride, floa
 // src_of[slot], its weight w[slot], its sign from the literal lit[slot].
 //  mode 0 (messages):  dst[r][dpos + f] = sum over positive edges of w * src[src][f]
 //                      dst[r][dneg + f] = sum over negative edges  (written)
+//                      and, with hcopy, dst[r][f] = hcopy[r][f] (the row's own state)
 //  mode 1 (transposes): dst[r][f] += sum_e w * src[src][(pos ? spos : sneg) + f]
+// The metadata of up to 64 edges is loaded lane-parallel (one edge per lane)
+// and broadcast with readlane, so that the feature loads of consecutive
+// edges do not wait on each other's index loads; the terms are added in edge
+// order.
 __global__ __launch_bounds__(256) void k_gather(int rows, int H, const int32_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ edges, const int32_t *__restrict__ src_of,
                                                 const int32_t *__restrict__ lit, const float *__restrict__ w,
                                                 const float *__restrict__ src, int sstride, int spos, int sneg,
-                                                float *dst, int dstride, int dpos, int dneg, int mode)
+                                                float *dst, int dstride, int dpos, int dneg, int mode,
+                                                const float *__restrict__ hcopy)
 {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int r = blockIdx.x * (blockDim.x >> 6) + wave;
     if (r >= rows) return;
     const int lane = threadIdx.x & 63;
     const int e0 = row_ptr[r], e1 = row_ptr[r + 1];
-    for (int f = lane; f < H; f += 64) {
+    for (int f0 = 0; f0 < H; f0 += 64) {
+        const int f = f0 + lane;
+        const bool fin = f < H;
+        const int fc = fin ? f : 0;
         float ap = 0.f, an = 0.f;
-        for (int e = e0; e < e1; ++e) {
-            const int slot = edges ? edges[e] : e;
-            const int sr = src_of[slot];
-            const bool pos = lit[slot] >= 0;
-            const float we = w[slot];
-            if (mode == 0) {
-                const float v = src[(size_t)sr * sstride + spos + f];
-                if (pos) ap += we * v; else an += we * v;
-            } else {
-                ap += we * src[(size_t)sr * sstride + (pos ? spos : sneg) + f];
+        for (int eb = e0; eb < e1; eb += 64) {
+            const int e = eb + lane;
+            int so = 0, pos = 1;
+            float we = 0.f;
+            if (e < e1) {
+                const int slot = edges ? edges[e] : e;
+                pos = lit[slot] >= 0 ? 1 : 0;
+                // element offset of the feature row this edge reads
+                so = src_of[slot] * sstride + (mode == 0 ? spos : (pos ? spos : sneg));
+                we = w[slot];
+            }
+            const int cnt = min(64, e1 - eb);
+            int q = 0;
+            for (; q + 4 <= cnt; q += 4) {
+                float v[4], wq[4];
+                int pq[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int o = __builtin_amdgcn_readlane(so, q + t);
+                    pq[t] = __builtin_amdgcn_readlane(pos, q + t);
+                    wq[t] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, we), q + t));
+                    v[t] = src[(size_t)o + fc];
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (mode == 0) {
+                        if (pq[t]) ap += wq[t] * v[t];
+                        else an += wq[t] * v[t];
+                    } else {
+                        ap += wq[t] * v[t];
+                    }
+                }
+            }
+            for (; q < cnt; ++q) {
+                const int o = __builtin_amdgcn_readlane(so, q);
+                const int pq = __builtin_amdgcn_readlane(pos, q);
+                const float wq = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, we), q));
+                const float v = src[(size_t)o + fc];
+                if (mode == 0) {
+                    if (pq) ap += wq * v;
+                    else an += wq * v;
+                } else {
+                    ap += wq * v;
+                }
             }
         }
+        if (!fin) continue;
         if (mode == 0) {
             dst[(size_t)r * dstride + dpos + f] = ap;
             dst[(size_t)r * dstride + dneg + f] = an;
+            if (hcopy) dst[(size_t)r * dstride + f] = hcopy[(size_t)r * H + f];
         } else {
             dst[(size_t)r * dstride + f] += ap;
         }
@@ -192,29 +249,11 @@ __global__ __launch_bounds__(256) void k_gather(int rows, int H, const int32_t *
 
 hipError_t gather(int rows, int H, const int32_t *row_ptr, const int32_t *edges, const int32_t *src_of,
                   const int32_t *lit, const float *w, const float *src, int sstride, int spos, int sneg, float *dst,
-                  int dstride, int dpos, int dneg, int mode, hipStream_t s)
+                  int dstride, int dpos, int dneg, int mode, hipStream_t s, const float *hcopy)
 {
     if (rows <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, H, row_ptr, edges, src_of,
-                       lit, w, src, sstride, spos, sneg, dst, dstride, dpos, dneg, mode);
-    return hipGetLastError();
-}
-
-// copy h (rows x H) into the first H columns of X (rows x 3H)
-__global__ void k_copy_cols(int64_t total, int H, const float *__restrict__ h, float *X, int xstride)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const int64_t r = i / H;
-    const int f = (int)(i - r * H);
-    X[(size_t)r * xstride + f] = h[i];
-}
-
-hipError_t copy_cols(int rows, int H, const float *h, float *X, int xstride, hipStream_t s)
-{
-    const int64_t total = (int64_t)rows * H;
-    if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, total, H, h, X, xstride);
+                       lit, w, src, sstride, spos, sneg, dst, dstride, dpos, dneg, mode, hcopy);
     return hipGetLastError();
 }
 

@@ -202,10 +202,8 @@ hipError_t weight_grad(ffsat_mpnn *net, int rows, int K, const float *X, int ldx
     while ((size_t)S * K * H > net->part_len && S > 1) S /= 2;
     hipError_t e = gemm(true, false, 0, K, H, rows, X, ldx, dZ, H, net->part, H, nullptr, S, (size_t)K * H, s);
     if (e != hipSuccess) return e;
-    int kslice = (rows + S - 1) / S;
-    kslice = ((kslice + 7) / 8) * 8;
-    const int used = std::max(1, (rows + kslice - 1) / kslice);
-    return sum_slices((int64_t)K * H, used, net->part, (size_t)K * H, out, false, s);
+    // exactly the slices the product wrote
+    return sum_slices((int64_t)K * H, gemm_slices(rows, S), net->part, (size_t)K * H, out, false, s);
 }
 
 ffsat_status forward(ffsat_mpnn *net, MpnnGraph *g, hipStream_t s)
@@ -217,13 +215,14 @@ ffsat_status forward(ffsat_mpnn *net, MpnnGraph *g, hipStream_t s)
     MCHK(gemm(false, false, 1, m, H, 8, g->fc, 8, W + o[P_EC], H, net->hc0, H, W + o[P_ECB], 1, 0, s));
     const float *hv = net->hv0, *hc = net->hc0;
     for (int r = 0; r < net->R; ++r) {
-        MCHK(copy_cols(m, H, hc, net->Xc[r], 3 * H, s));
-        MCHK(gather(m, H, g->con_ptr, nullptr, g->var_of, g->lit, g->wk, hv, H, 0, 0, net->Xc[r], 3 * H, H, 2 * H, 0, s));
+        // messages into columns H..3H of X, the constraint's own state into 0..H
+        MCHK(gather(m, H, g->con_ptr, nullptr, g->var_of, g->lit, g->wk, hv, H, 0, 0, net->Xc[r], 3 * H, H, 2 * H, 0, s,
+                    hc));
         MCHK(gemm(false, false, 1, m, H, 3 * H, net->Xc[r], 3 * H, W + o[p_wc(r)], H, net->Hc[r], H, W + o[p_bc(r)], 1,
                   0, s));
         hc = net->Hc[r];
-        MCHK(copy_cols(n, H, hv, net->Xv[r], 3 * H, s));
-        MCHK(gather(n, H, g->vptr, g->vslots, g->con_of, g->lit, g->wd, hc, H, 0, 0, net->Xv[r], 3 * H, H, 2 * H, 0, s));
+        MCHK(gather(n, H, g->vptr, g->vslots, g->con_of, g->lit, g->wd, hc, H, 0, 0, net->Xv[r], 3 * H, H, 2 * H, 0, s,
+                    hv));
         MCHK(gemm(false, false, 1, n, H, 3 * H, net->Xv[r], 3 * H, W + o[p_wv(r)], H, net->Hv[r], H, W + o[p_bv(r)], 1,
                   0, s));
         hv = net->Hv[r];

@@ -9,11 +9,12 @@ namespace ffsat {
 
 hipError_t gemm(bool ta, bool tb, int epi, int M, int N, int K, const float *A, int lda, const float *B, int ldb,
                 float *C, int ldc, const float *bias, int splits, size_t slice_stride, hipStream_t s);
+// number of reduction slices gemm() writes for `splits` requested over K terms
+int gemm_slices(int K, int splits);
 hipError_t sum_slices(int64_t len, int S, const float *part, size_t stride, float *out, bool add, hipStream_t s);
 hipError_t gather(int rows, int H, const int32_t *row_ptr, const int32_t *edges, const int32_t *src_of,
                   const int32_t *lit, const float *w, const float *src, int sstride, int spos, int sneg, float *dst,
-                  int dstride, int dpos, int dneg, int mode, hipStream_t s);
-hipError_t copy_cols(int rows, int H, const float *h, float *X, int xstride, hipStream_t s);
+                  int dstride, int dpos, int dneg, int mode, hipStream_t s, const float *hcopy = nullptr);
 hipError_t relu_back(int rows, int H, float *dH, const float *Y, const float *dx, int dxstride, hipStream_t s);
 hipError_t colsum(int rows, int H, const float *X, float *part, int max_slices, float *out, hipStream_t s);
 hipError_t head(int n, int H, const float *hv, const float *wo, const float *bo, float *mu, hipStream_t s);
