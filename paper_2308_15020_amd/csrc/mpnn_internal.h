@@ -30,6 +30,7 @@ hipError_t propose(int64_t total, int B, int nl, const float *mu, float sigma, u
 // Incidence graph of a problem in original constraint order, on the device.
 struct MpnnGraph {
     int n = 0, m = 0, nnz = 0;
+    void *buf = nullptr;          // one device allocation holding every array below
     int32_t *con_ptr = nullptr;   // [m+1]
     int32_t *lit = nullptr;       // [nnz] var | negated << 31
     int32_t *var_of = nullptr;    // [nnz] variable of each slot
