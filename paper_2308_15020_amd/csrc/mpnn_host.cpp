@@ -89,6 +89,12 @@ void free_ws(ffsat_mpnn *net)
 ffsat_status ensure_ws(ffsat_mpnn *net, int n, int m)
 {
     if (n <= net->cap_n && m <= net->cap_m) return FFSAT_OK;
+    // grow with a quarter of headroom, so that a stream of similar instances
+    // (a test set, training batches) does not reallocate on every larger one
+    n = std::max(n, net->cap_n);
+    m = std::max(m, net->cap_m);
+    n += n / 4;
+    m += m / 4;
     free_ws(net);
     const int H = net->H;
     auto get = [&](size_t count, float **dst) -> ffsat_status {
