@@ -293,6 +293,56 @@ def test_grouped_launch_matches_per_bin_launches(ffs, mixed, mode):
         assert np.array_equal(ca[k], cb[k]), k
 
 
+@pytest.mark.parametrize("mode,gc,gf", [("group_all", 4, 1), ("group_all", 16, 1), ("group_all", 8, 4),
+                                         ("group_dft", 0, 4), ("group_dft", 0, 1)])
+def test_grouped_shapes_match_per_bin_launches(ffs, mixed, tmp_path, mode, gc, gf):
+    """Every grouped shape the tuner may pick (transform-free constraints per
+    wave inside the all-bin group, root-of-unity frequency split), forced
+    through the tune cache, against one launch per bin: FP32 tolerance for
+    values, exact for the check; the fused iterations stay bitwise equal
+    between graph replay and eager launches."""
+    import json
+    inst, prob = mixed
+    B = 96
+    cache = str(tmp_path / "tune.json")
+    ffs.Plan(prob, B, autotune=True, tune_cache=cache, mode=mode).close()
+    c = json.load(open(cache))
+    key = [k for k in c if "|mode|" in k]
+    assert len(key) == 1
+    codes = {"group_all": 2, "group_dft": 3}
+    c[key[0]] = [codes[mode], 0, 8 * gc + gf]
+    json.dump(c, open(cache, "w"))
+    pg = ffs.Plan(prob, B, autotune=True, tune_cache=cache, mode=mode)
+    d = pg.describe()
+    assert d["tuned_modes"] == [] and (d["group_real_cpw"], d["group_dft_fg"]) == (gc, gf)
+    ing = [b for b in d["bins"]["f32"] if b["in_group"]]
+    assert ing and all(b["fg"] == gf for b in ing if b["class"] == "dft")
+    if mode == "group_all":
+        assert any(b["class"] == "real" for b in ing)
+    pb = ffs.Plan(prob, B, mode="per_bin")
+    x = torch.from_numpy(points(inst, B, 91, "mixed_edge")).to(DEV)
+    a = to_np(pg.eval(x, want_con=True))
+    b = to_np(pb.eval(x, want_con=True))
+    S = var_scale(inst)[:, None]
+    assert np.max(np.abs(a["grad"] - b["grad"]) / S) <= TOL32
+    assert np.max(np.abs(a["con_val"] - b["con_val"])) <= TOL32
+    assert np.max(np.abs(a["F"] - b["F"])) <= 1e-6 * np.abs(inst.weights).sum()
+    ca, cb = to_np(pg.round_check(x)), to_np(pb.round_check(x))
+    for k in ("n_sat", "unsat_bits", "U"):
+        assert np.array_equal(ca[k], cb[k]), k
+    w0 = prob.get_weights().clone()
+    xr, xe = x.clone(), x.clone()
+    orr = pg.run_iters(xr, 3, 0.05, 0.4)
+    wr = prob.get_weights().clone()
+    prob.set_weights(w0.cpu().numpy())
+    pe = ffs.Plan(prob, B, autotune=True, tune_cache=cache, mode=mode, use_graphs=False)
+    oe = pe.run_iters(xe, 3, 0.05, 0.4)
+    torch.cuda.synchronize()
+    assert torch.equal(xr, xe) and torch.equal(wr, prob.get_weights())
+    assert torch.equal(orr["F"], oe["F"]) and torch.equal(orr["n_sat"], oe["n_sat"])
+    prob.set_weights(inst.weights)
+
+
 def test_run_iters_graph_equals_eager(ffs, mixed):
     """Graph-replayed fused iterations (with ERWA) against the same calls made
     eagerly: bitwise, on three replays with eager work and syncs between."""
