@@ -116,7 +116,10 @@ typedef struct {
                                 (no internal side streams); reserved[1]: launch
                                 structure of the FP32 evaluation, 0 automatic (the
                                 autotuner times the others and keeps the fastest;
-                                without it 2, or 3 when reserved[2] is 2 or 3),
+                                without it 2, or 3 when reserved[2] is 2 or 3;
+                                the bins inside a grouped launch then take 8
+                                transform-free constraints per wave and one wave
+                                per root-of-unity unit),
                                 1 one launch per bin, 2 one grouped launch for all
                                 bins, 3 a grouped launch for the root-of-unity bins
                                 with the others beside it; reserved[2]: gradient of
@@ -177,7 +180,14 @@ ffsat_status ffsat_get_weights(const ffsat_problem *p, float *w, int32_t on_devi
 ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffsat_plan_opts *opts,
                                ffsat_plan **out);
 ffsat_status ffsat_plan_destroy(ffsat_plan *plan);
-/* Runs the tile-shape autotuner now (synchronises the stream). */
+/* Runs the tile-shape autotuner now (synchronises the stream): per bin,
+ * constraints per wave, waves per block and frequency split, each bin timed
+ * in launches of its own; then, timed over four fused iterations, the
+ * launch structure (when automatic), the pull class (when automatic) and the
+ * shapes of the bins inside a grouped launch (transform-free constraints per
+ * wave 4, 8 or 16 in the all-bin group; root-of-unity frequency split 1 or
+ * 4), which replace the per-bin shapes of those bins.  Results go to the
+ * plan's tune cache (in memory, and the JSON file when one is named). */
 ffsat_status ffsat_plan_tune(ffsat_plan *plan, void *stream);
 /* Writes a JSON description of the bins and their tile shapes into buf
  * (truncated to len-1 characters, always NUL-terminated). */
