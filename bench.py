@@ -242,6 +242,15 @@ def measure(name, args, dev, headline):
             ent = roofline_entry(label, flop, nbytes, "f32", avg_s, per_step)
             ent["flop_exact_per_launch"] = sum(bin_flop_exact(b, B) for b in grp)
             ent["kernel_name"] = "k_eval_group"
+        elif k["bin"] == -4:
+            grp = [b for b in bins if b.get("in_group64")]
+            flop = sum(bin_work(b, B)[0] for b in grp)
+            nbytes = sum(bin_work(b, B)[1] for b in grp)
+            label = (f"grouped FP64 root-of-unity launch ({len(grp)} bins, {sum(b['count'] for b in grp)} constraints, "
+                     f"len <= {max(b['maxk'] for b in grp)})")
+            ent = roofline_entry(label, flop, nbytes, "f64", avg_s, per_step)
+            ent["flop_exact_per_launch"] = sum(bin_flop_exact(b, B) for b in grp)
+            ent["kernel_name"] = "k_eval_group64"
         elif k["bin"] >= 0:
             bd = bins[k["bin"]]
             flop, nbytes, dt = bin_work(bd, B)

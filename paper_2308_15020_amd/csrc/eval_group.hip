@@ -1,5 +1,6 @@
-// Grouped evaluation launch: every FP32-arithmetic bin of the FP32
-// evaluation in one grid.  A host-built block table gives each 4-wave block
+// Grouped evaluation launches: every FP32-arithmetic bin of the FP32
+// evaluation in one grid, and the long FP64-arithmetic root-of-unity bins in
+// another.  A host-built block table gives each 4-wave block
 // its bin (entry) and first unit; the host orders the blocks longest-first
 // with the memory-bound real-chain blocks spread among them.  One launch
 // keeps all CUs busy across bins of very different cost, with no
@@ -62,6 +63,60 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #undef X
     default: break;
     }
+}
+
+// The long root-of-unity bins with FP64 arithmetic (k > 256 by default) in
+// one grid as well: their kernels all run at 2 waves per SIMD, so one grid
+// costs no occupancy, and the ramp and tail of a launch are paid once
+// instead of once per bin.  (SEG, L): 14 or 16 at L = 32, 18..24 at L = 16.
+#define FFSAT_GROUP64_SHAPES(X)                                                                           \
+    X(0, 14, 32) X(1, 16, 32) X(2, 18, 16) X(3, 20, 16) X(4, 22, 16) X(5, 24, 16)
+
+int group_variant64(int seg, int L)
+{
+#define X(ID, S, LL) \
+    if (seg == S && L == LL) return ID;
+    FFSAT_GROUP64_SHAPES(X)
+#undef X
+    return -1;
+}
+
+__global__ __launch_bounds__(256) void k_eval_group64(EvalArgs<float> a, const float *__restrict__ xin,
+                                                      const ConDesc *__restrict__ con,
+                                                      const int32_t *__restrict__ lits,
+                                                      const float *__restrict__ wts,
+                                                      const TypeT<double> *__restrict__ types,
+                                                      const FreqT<double> *__restrict__ freqs,
+                                                      const GroupEntry *__restrict__ ent,
+                                                      const int2 *__restrict__ blk)
+{
+    extern __shared__ __align__(16) char group_lds[];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int2 bw = blk[blockIdx.x];
+    const GroupEntry e = ent[__builtin_amdgcn_readfirstlane(bw.x)];
+    const Span sp{e.first, e.count, e.cpw, e.n_rb, e.fpart_row0};
+    const int fg = e.fg;
+    const int unit = fg > 1 ? bw.y : bw.y + wave;
+    const int wg = fg > 1 ? wave : 0;
+    switch (e.variant) {
+#define X(ID, S, LL)                                                                                          \
+    case ID:                                                                                                  \
+        eval_unit<float, double, S, LL, true>(a, sp, unit, xin, con, lits, wts, types, freqs, fg, wg, group_lds); \
+        break;
+        FFSAT_GROUP64_SHAPES(X)
+#undef X
+    default: break;
+    }
+}
+
+hipError_t launch_eval_group64_f32(const EvalArgs<float> &a, const GroupEntry *ent, const int2 *blk, int nblk,
+                                   size_t lds, hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eval_group64, dim3((unsigned)nblk), dim3(256), lds, s, a, a.x, a.con, a.lit, a.w,
+                       reinterpret_cast<const TypeT<double> *>(a.types),
+                       reinterpret_cast<const FreqT<double> *>(a.freqs), ent, blk);
+    return hipGetLastError();
 }
 
 hipError_t launch_eval_group_f32(const EvalArgs<float> &a, const GroupEntry *ent, const int2 *blk, int nblk,

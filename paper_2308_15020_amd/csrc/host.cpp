@@ -1134,6 +1134,12 @@ static void prof_end(ffsat_plan *pl, hipStream_t s, ProfRec &r)
     pl->prof_pending.push_back(r);
 }
 
+// Root-of-unity bins with FP64 arithmetic that the FP64 grouped launch can hold.
+static bool in_group64(const Bin &b)
+{
+    return !b.uc && b.ct == CT_F64 && b.cls == CLASS_DFT && group_variant64(b.seg, b.L) >= 0;
+}
+
 // Block table of the grouped FP32 evaluation (MODE_GROUP_ALL: every bin with
 // a grouped variant; MODE_GROUP_DFT: the root-of-unity bins, the others run
 // on a side stream beside it).  Units of a bin are (chunk,
@@ -1141,29 +1147,52 @@ static void prof_end(ffsat_plan *pl, hipStream_t s, ProfRec &r)
 // frequencies over 4 waves (fg = 4).  Blocks are ordered longest first
 // (estimated VALU work), with the real-chain blocks spread evenly among the
 // root-of-unity ones so that every CU mixes memory- and ALU-bound waves.
+// The FP64-arithmetic root-of-unity bins with a variant of the FP64 group
+// get a block table of their own, longest first.
 static ffsat_status build_groups(ffsat_plan *pl)
 {
     (void)hipFree(pl->d_gent);
     (void)hipFree(pl->d_gblk);
+    (void)hipFree(pl->d_gent64);
+    (void)hipFree(pl->d_gblk64);
     pl->d_gent = nullptr;
     pl->d_gblk = nullptr;
+    pl->d_gent64 = nullptr;
+    pl->d_gblk64 = nullptr;
     pl->gblocks = 0;
     pl->glds = 0;
+    pl->gblocks64 = 0;
+    pl->glds64 = 0;
     pl->gsolo.clear();
     if (!pl->grouped) return FFSAT_OK;
     const std::vector<Bin> &bins = pl->bins[IO_F32];
-    std::vector<GroupEntry> ent;
+    std::vector<GroupEntry> ent, ent64;
     struct Blk {
         int2 b;
         double cost;
     };
-    std::vector<Blk> dft, real;
+    std::vector<Blk> dft, real, f64;
     int row0 = 0;
     for (int i = 0; i < (int)bins.size(); ++i) {
         const Bin &b = bins[i];
+        const int rows = (b.count + b.cpw - 1) / b.cpw;
+        if (in_group64(b) && (b.fg == 1 || b.fg == 4)) {
+            // the FP64 group: blocks of 4 units (fg 1) or one unit over 4
+            // waves (fg 4), longest first
+            const int rpw = 64 / b.L;
+            const int n_rb = (pl->B + rpw - 1) / rpw;
+            const int ei = (int)ent64.size();
+            ent64.push_back(GroupEntry{group_variant64(b.seg, b.L), b.first, b.count, b.cpw, n_rb, row0, b.fg, 0});
+            const int64_t units = (int64_t)rows * n_rb;
+            const double unit_cost = b.cost / std::max(1, b.count) * b.cpw * rpw;
+            for (int64_t u = 0; u < units; u += (b.fg == 4 ? 1 : 4))
+                f64.push_back({make_int2(ei, (int)u), b.fg == 4 ? unit_cost : 4 * unit_cost});
+            if (b.fg == 4) pl->glds64 = std::max(pl->glds64, (size_t)3 * (b.seg + 1) * 64 * sizeof(double));
+            row0 += rows;
+            continue;
+        }
         const int v = b.uc ? -1 : group_variant(b.ct, b.cls, b.seg, b.L);
         const int fg = b.cls == CLASS_DFT ? b.fg : 1;
-        const int rows = (b.count + b.cpw - 1) / b.cpw;
         if (v < 0 || (fg != 1 && fg != 4) || (pl->mode == MODE_GROUP_DFT && b.cls != CLASS_DFT)) {
             pl->gsolo.push_back(i);
             row0 += rows;
@@ -1184,6 +1213,17 @@ static ffsat_status build_groups(ffsat_plan *pl)
                 (b.cls == CLASS_DFT ? dft : real).push_back({make_int2(ei, (int)u), 4 * unit_cost});
         }
         row0 += rows;
+    }
+    if (!ent64.empty()) {
+        std::stable_sort(f64.begin(), f64.end(), [](const Blk &x, const Blk &y) { return x.cost > y.cost; });
+        std::vector<int2> order64;
+        order64.reserve(f64.size());
+        for (const Blk &q : f64) order64.push_back(q.b);
+        HIPCHK(hipMalloc(&pl->d_gent64, ent64.size() * sizeof(GroupEntry)));
+        HIPCHK(hipMemcpy(pl->d_gent64, ent64.data(), ent64.size() * sizeof(GroupEntry), hipMemcpyHostToDevice));
+        HIPCHK(hipMalloc(&pl->d_gblk64, order64.size() * sizeof(int2)));
+        HIPCHK(hipMemcpy(pl->d_gblk64, order64.data(), order64.size() * sizeof(int2), hipMemcpyHostToDevice));
+        pl->gblocks64 = (int)order64.size();
     }
     if (ent.empty()) return FFSAT_OK;
     std::stable_sort(dft.begin(), dft.end(), [](const Blk &x, const Blk &y) { return x.cost > y.cost; });
@@ -1217,7 +1257,7 @@ static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream
     const Layout &Ly = pl->p->lay[io];
     const std::vector<Bin> &bins = pl->bins[io];
     if constexpr (sizeof(IO) == 4) {
-        if (pl->grouped && pl->gblocks > 0) {
+        if (pl->grouped && (pl->gblocks > 0 || pl->gblocks64 > 0)) {
             // bins without a grouped variant: on a side stream beside the
             // grouped launch when there is one, else before it
             hipError_t e;
@@ -1228,6 +1268,16 @@ static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream
                 if ((e = hipEventRecord(pl->ev_fork, s)) != hipSuccess) return e;
                 if ((e = hipStreamWaitEvent(pl->side[0], pl->ev_fork, 0)) != hipSuccess) return e;
                 ss = pl->side[0];
+            }
+            if (pl->gblocks64 > 0) {
+                // the long FP64 root-of-unity bins first: the heaviest work
+                a.types = (const void *)Ly.d_t64;
+                a.freqs = (const void *)Ly.d_f64;
+                ProfRec rec;
+                prof_begin(pl, ss, prof_active(pl, s), rec, io, -4);
+                e = launch_eval_group64_f32(a, pl->d_gent64, pl->d_gblk64, pl->gblocks64, pl->glds64, ss);
+                prof_end(pl, ss, rec);
+                if (e != hipSuccess) return e;
             }
             for (int bi : pl->gsolo) {
                 const Bin &b = bins[bi];
@@ -1248,13 +1298,15 @@ static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream
                 prof_end(pl, ss, rec);
                 if (e != hipSuccess) return e;
             }
-            a.types = (const void *)Ly.d_t32;
-            a.freqs = (const void *)Ly.d_f32;
-            ProfRec rec;
-            prof_begin(pl, s, prof_active(pl, s), rec, io, -2);
-            e = launch_eval_group_f32(a, pl->d_gent, pl->d_gblk, pl->gblocks, pl->glds, s);
-            prof_end(pl, s, rec);
-            if (e != hipSuccess) return e;
+            if (pl->gblocks > 0) {
+                a.types = (const void *)Ly.d_t32;
+                a.freqs = (const void *)Ly.d_f32;
+                ProfRec rec;
+                prof_begin(pl, s, prof_active(pl, s), rec, io, -2);
+                e = launch_eval_group_f32(a, pl->d_gent, pl->d_gblk, pl->gblocks, pl->glds, s);
+                prof_end(pl, s, rec);
+                if (e != hipSuccess) return e;
+            }
             if (fork) {
                 if ((e = hipEventRecord(pl->ev_join[0], pl->side[0])) != hipSuccess) return e;
                 if ((e = hipStreamWaitEvent(s, pl->ev_join[0], 0)) != hipSuccess) return e;
@@ -1376,6 +1428,7 @@ constexpr int GROUP_DFT_FG = 1;
 constexpr int GROUP_CODE_MAX = 8 * 64 + 7;   // cache code of the grouped shapes: 8 * chain cpw + fg
 static bool in_group(const ffsat_plan *pl, const Bin &b)
 {
+    if (in_group64(b)) return true;
     if (b.uc || group_variant(b.ct, b.cls, b.seg, b.L) < 0) return false;
     return b.cls == CLASS_DFT || pl->mode == MODE_GROUP_ALL;
 }
@@ -1869,6 +1922,8 @@ extern "C" ffsat_status ffsat_plan_destroy(ffsat_plan *pl)
     (void)hipFree(pl->d_tune_u);
     (void)hipFree(pl->d_gent);
     (void)hipFree(pl->d_gblk);
+    (void)hipFree(pl->d_gent64);
+    (void)hipFree(pl->d_gblk64);
     for (int io = 0; io < 2; ++io) {
         (void)hipFree(pl->d_slot[io]);
         (void)hipFree(pl->d_fpart[io]);
@@ -1910,7 +1965,7 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
     o << "{\"B\": " << pl->B << ", \"tuned\": " << (pl->tuned ? "true" : "false") << ", \"mode\": \""
       << mode_names[pl->mode] << "\"" << ", \"mode_auto\": " << (pl->mode_auto ? "true" : "false")
       << ", \"grouped\": " << (pl->grouped && pl->gblocks > 0 ? "true" : "false") << ", \"group_blocks\": " << pl->gblocks
-      << ", \"solo_bins\": " << pl->gsolo.size() << ", \"graphs_cached\": " << pl->graphs.size()
+      << ", \"group64_blocks\": " << pl->gblocks64 << ", \"solo_bins\": " << pl->gsolo.size() << ", \"graphs_cached\": " << pl->graphs.size()
       << ", \"graph_captures\": " << pl->captures << ", \"pull\": " << PULL_K[pl->pull]
       << ", \"pull_auto\": " << (pl->pull_auto ? "true" : "false") << ", \"pull_vc\": " << pl->pull_vc
       << ", \"pull_entries\": " << (pl->pull ? pl->p->lay[IO_F32].pull[pl->pull].n_ent : 0)
@@ -1934,11 +1989,12 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
               << ", \"k2_per_restart\": " << b.k2
               << ", \"pull_class\": " << b.pk << ", \"pulled\": " << (io == IO_F32 && pl->pull && b.pk >= pl->pull ? "true" : "false")
               << ", \"cpw\": " << b.cpw
-              << ", \"wpb\": " << b.wpb << ", \"fg\": " << b.fg << ", \"in_group\": "
-              << ((io == IO_F32 && pl->grouped && pl->gblocks > 0 &&
-                   std::find(pl->gsolo.begin(), pl->gsolo.end(), (int)i) == pl->gsolo.end())
-                      ? "true"
-                      : "false")
+              << ", \"wpb\": " << b.wpb << ", \"fg\": " << b.fg;
+            // the grouped launch that evaluates the bin, if any
+            const bool g64 = io == IO_F32 && pl->grouped && pl->gblocks64 > 0 && in_group64(b) && (b.fg == 1 || b.fg == 4);
+            const bool g32 = io == IO_F32 && pl->grouped && pl->gblocks > 0 && !g64 &&
+                             std::find(pl->gsolo.begin(), pl->gsolo.end(), (int)i) == pl->gsolo.end();
+            o << ", \"in_group\": " << (g32 ? "true" : "false") << ", \"in_group64\": " << (g64 ? "true" : "false")
               << "}";
         }
         o << "]";

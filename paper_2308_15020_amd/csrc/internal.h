@@ -240,6 +240,10 @@ struct ffsat_plan {
     int2 *d_gblk = nullptr;
     int gblocks = 0;
     size_t glds = 0;
+    ffsat::GroupEntry *d_gent64 = nullptr;   // the FP64 root-of-unity group (grouped structures)
+    int2 *d_gblk64 = nullptr;
+    int gblocks64 = 0;
+    size_t glds64 = 0;
     std::vector<int> gsolo;          // bin indices launched on their own
     // three side streams: with the caller's stream, one per hardware queue
     // of HIP's default of four per process
@@ -289,6 +293,10 @@ hipError_t launch_eval_bin_f64(const Bin &bin, const EvalArgs<double> &a, hipStr
 int group_variant(int ct, int cls, int seg, int L);
 hipError_t launch_eval_group_f32(const EvalArgs<float> &a, const GroupEntry *ent, const int2 *blk, int nblk,
                                  size_t lds, hipStream_t s);
+// the long FP64-arithmetic root-of-unity bins of the FP32 evaluation
+int group_variant64(int seg, int L);
+hipError_t launch_eval_group64_f32(const EvalArgs<float> &a, const GroupEntry *ent, const int2 *blk, int nblk,
+                                   size_t lds, hipStream_t s);
 bool eval_variant_exists(int io, int ct, int cls, int seg, int L, bool uc);
 
 // Reduction after the evaluation kernels: gradient (or fused projected step
