@@ -648,9 +648,10 @@ struct EvalFn {
 // Segment shapes.  FP32 arithmetic: L = 1 with SEG in {4, 8, ..., 32}, L >= 2
 // with SEG in {16, 20, 24, 28, 32}.  FP64 arithmetic: L = 1 with SEG in
 // {4, 8, ..., 24}; L = 2..8 with SEG in {16, 20, 24}; L = 16 with every even
-// SEG from 14 to 24 and L = 32 with SEG 14 or 16 (the long root-of-unity
+// SEG from 14 to 26 and L = 32 with SEG 14 or 16 (the long root-of-unity
 // bins, where a padding position costs as much as a literal in every
-// frequency).
+// frequency; 26 positions at 16 lanes still fit 2 waves per SIMD, 28 do
+// not).
 template <typename IO, typename CT, int SEG, int L, bool CPLX>
 static EvalFn<IO> handle()
 {
@@ -674,6 +675,7 @@ static EvalFn<IO> pick_L(int seg)
     case 20: if constexpr (!F64 || L <= 16) return handle<IO, CT, 20, L, CPLX>(); break;
     case 22: if constexpr (F64 && L == 16) return handle<IO, CT, 22, L, CPLX>(); break;
     case 24: if constexpr (!F64 || L <= 16) return handle<IO, CT, 24, L, CPLX>(); break;
+    case 26: if constexpr (F64 && L == 16) return handle<IO, CT, 26, L, CPLX>(); break;
     case 28: if constexpr (!F64) return handle<IO, CT, 28, L, CPLX>(); break;
     case 32: if constexpr (!F64) return handle<IO, CT, 32, L, CPLX>(); break;
     default: break;

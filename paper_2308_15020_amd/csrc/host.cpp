@@ -460,6 +460,9 @@ void shape_for(int ct, int k, int &seg, int &L)
     if (ct == CT_F64) {
         L = 1;
         while ((k + L - 1) / L > 24 && L < 32) L <<= 1;
+        // 16 lanes of up to 26 positions before 32 lanes: a butterfly stage
+        // less per frequency and less padding (k <= 416)
+        if (L == 32 && (k + 15) / 16 <= 26) L = 16;
         const int s = (k + L - 1) / L;
         if (L >= 16) seg = std::max(14, ((s + 1) / 2) * 2);
         else if (L > 1) seg = std::max(16, ((s + 3) / 4) * 4);

@@ -15,7 +15,7 @@ TOL64 = 1e-12
 
 def every_bin_instance(seed=11, n=700):
     """Short and long constraints of every kind: all segment counts of the
-    FP32 and FP64 kernels (FP64 root-of-unity shapes 14..24 positions over
+    FP32 and FP64 kernels (FP64 root-of-unity shapes 14..26 positions over
     16 lanes, 14 and 16 over 32), thresholds outside [1, k], length-1
     constraints."""
     base = random_hybrid(n, seed, n_or=150, or_len=(1, 9), n_xor=60, xor_len=(1, 40),
@@ -25,7 +25,8 @@ def every_bin_instance(seed=11, n=700):
     for kind, k, t in [(2, 512, 200), (2, 400, 133), (2, 300, 299), (2, 257, 128), (2, 256, 100),
                        (2, 255, 7), (2, 200, 100), (0, 512, 0), (1, 511, 1), (1, 300, 0),
                        (2, 64, 64), (2, 65, 1), (2, 33, 34), (0, 17, 0), (1, 64, 1),
-                       (2, 340, 170), (2, 384, 1), (2, 449, 224), (2, 180, 90), (2, 47, 20), (1, 46, 1)]:
+                       (2, 340, 170), (2, 384, 1), (2, 449, 224), (2, 180, 90), (2, 47, 20), (1, 46, 1),
+                       (2, 430, 215)]:
         v = rng.choice(n, size=k, replace=False) + 1
         sg = np.where(rng.random(k) < 0.5, -1, 1)
         extra.append((kind, [t], [(v * sg).astype(np.int32)]))
