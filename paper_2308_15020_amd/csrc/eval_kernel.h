@@ -647,8 +647,8 @@ struct EvalFn {
 
 // Segment shapes.  FP32 arithmetic: L = 1 with SEG in {4, 8, ..., 32}, L >= 2
 // with SEG in {16, 20, 24, 28, 32}.  FP64 arithmetic: L = 1 with SEG in
-// {4, 8, ..., 24}; L = 2..8 with SEG in {16, 20, 24}; L = 16 with every even
-// SEG from 14 to 26 and L = 32 with SEG 14 or 16 (the long root-of-unity
+// {4, 8, ..., 24}; L = 2..8 with SEG in {16, 20, 24}; L = 16 with every SEG
+// from 14 to 26 and L = 32 with SEG 14, 15 or 16 (the long root-of-unity
 // bins, where a padding position costs as much as a literal in every
 // frequency; 26 positions at 16 lanes still fit 2 waves per SIMD, 28 do
 // not).
@@ -670,11 +670,17 @@ static EvalFn<IO> pick_L(int seg)
     case 8: if constexpr (L == 1) return handle<IO, CT, 8, L, CPLX>(); break;
     case 12: if constexpr (L == 1) return handle<IO, CT, 12, L, CPLX>(); break;
     case 14: if constexpr (F64 && L >= 16) return handle<IO, CT, 14, L, CPLX>(); break;
+    case 15: if constexpr (F64 && L >= 16) return handle<IO, CT, 15, L, CPLX>(); break;
     case 16: return handle<IO, CT, 16, L, CPLX>();
+    case 17: if constexpr (F64 && L == 16) return handle<IO, CT, 17, L, CPLX>(); break;
     case 18: if constexpr (F64 && L == 16) return handle<IO, CT, 18, L, CPLX>(); break;
+    case 19: if constexpr (F64 && L == 16) return handle<IO, CT, 19, L, CPLX>(); break;
     case 20: if constexpr (!F64 || L <= 16) return handle<IO, CT, 20, L, CPLX>(); break;
+    case 21: if constexpr (F64 && L == 16) return handle<IO, CT, 21, L, CPLX>(); break;
     case 22: if constexpr (F64 && L == 16) return handle<IO, CT, 22, L, CPLX>(); break;
+    case 23: if constexpr (F64 && L == 16) return handle<IO, CT, 23, L, CPLX>(); break;
     case 24: if constexpr (!F64 || L <= 16) return handle<IO, CT, 24, L, CPLX>(); break;
+    case 25: if constexpr (F64 && L == 16) return handle<IO, CT, 25, L, CPLX>(); break;
     case 26: if constexpr (F64 && L == 16) return handle<IO, CT, 26, L, CPLX>(); break;
     case 28: if constexpr (!F64) return handle<IO, CT, 28, L, CPLX>(); break;
     case 32: if constexpr (!F64) return handle<IO, CT, 32, L, CPLX>(); break;

@@ -464,7 +464,7 @@ void shape_for(int ct, int k, int &seg, int &L)
         // less per frequency and less padding (k <= 416)
         if (L == 32 && (k + 15) / 16 <= 26) L = 16;
         const int s = (k + L - 1) / L;
-        if (L >= 16) seg = std::max(14, ((s + 1) / 2) * 2);
+        if (L >= 16) seg = std::max(14, s);   // every count: padding costs as much as a literal
         else if (L > 1) seg = std::max(16, ((s + 3) / 4) * 4);
         else seg = s <= 4 ? 4 : ((s + 3) / 4) * 4;
         return;
