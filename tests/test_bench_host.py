@@ -64,7 +64,7 @@ def test_profsum_cards(tmp_path):
     assert card["source_sha256"] == profsum.kernel_source_hash()
 
 
-@pytest.mark.parametrize("workload,kernel", [("large", "k_eval<float, double, 16, 32, true>"),
+@pytest.mark.parametrize("workload,kernel", [("large", "k_eval_group64"),
                                              ("large3sat", "k_pull<4, 4, true>"),
                                              ("mixed2000", "k_eval_group")])
 def test_committed_cards_cover_dominant_kernels(workload, kernel):
