@@ -10,15 +10,17 @@
 namespace ffsat {
 
 // Kernel variants of a grouped launch (FP32 arithmetic, the shapes of the
-// FP32 shape rule): (SEG, L) for L = 1 with SEG in {4, 8, 16, 24}, and for
-// L in {2, 4, 8, 16} with SEG in {16, 24}; real chains first, then
+// FP32 shape rule): (SEG, L) for L = 1 with SEG in {4, 8, ..., 24}, and for
+// L in {2, 4, 8, 16} with SEG in {16, 20, 24}; real chains first, then
 // root-of-unity products.
-#define FFSAT_GROUP_SHAPES(X, CPLX, BASE)                                                             \
-    X(BASE + 0, 4, 1, CPLX) X(BASE + 1, 8, 1, CPLX) X(BASE + 2, 16, 1, CPLX) X(BASE + 3, 24, 1, CPLX) \
-    X(BASE + 4, 16, 2, CPLX) X(BASE + 5, 24, 2, CPLX) X(BASE + 6, 16, 4, CPLX)                        \
-    X(BASE + 7, 24, 4, CPLX) X(BASE + 8, 16, 8, CPLX) X(BASE + 9, 24, 8, CPLX)                        \
-    X(BASE + 10, 16, 16, CPLX) X(BASE + 11, 24, 16, CPLX)
-constexpr int GROUP_SHAPES = 12;
+#define FFSAT_GROUP_SHAPES(X, CPLX, BASE)                                                              \
+    X(BASE + 0, 4, 1, CPLX) X(BASE + 1, 8, 1, CPLX) X(BASE + 2, 12, 1, CPLX) X(BASE + 3, 16, 1, CPLX)  \
+    X(BASE + 4, 20, 1, CPLX) X(BASE + 5, 24, 1, CPLX) X(BASE + 6, 16, 2, CPLX) X(BASE + 7, 20, 2, CPLX) \
+    X(BASE + 8, 24, 2, CPLX) X(BASE + 9, 16, 4, CPLX) X(BASE + 10, 20, 4, CPLX)                        \
+    X(BASE + 11, 24, 4, CPLX) X(BASE + 12, 16, 8, CPLX) X(BASE + 13, 20, 8, CPLX)                      \
+    X(BASE + 14, 24, 8, CPLX) X(BASE + 15, 16, 16, CPLX) X(BASE + 16, 20, 16, CPLX)                    \
+    X(BASE + 17, 24, 16, CPLX)
+constexpr int GROUP_SHAPES = 18;
 
 int group_variant(int ct, int cls, int seg, int L)
 {

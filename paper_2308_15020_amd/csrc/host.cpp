@@ -449,13 +449,15 @@ void shape_for_uc(int k, int &seg, int &L)
 
 // Segment shape of a constraint of length k: L lanes (a power of two) of SEG
 // positions each, L * SEG >= k, the smallest such L and then the smallest
-// SEG.  FP32 arithmetic: SEG in {4, 8, 16, 24} (32 past k = 384).  FP64
+// SEG.  FP32 arithmetic: SEG in {4, 8, 16, 24} (32 past k = 384); products
+// at roots of unity (dft) also take 12 on one lane and 20 on several.  FP64
 // arithmetic: SEG up to 24 (multiples of 4 below 16 lanes), 16-lane groups
-// take every even SEG from 14 to 24 and 32-lane groups (k > 384) 14 or 16:
-// in the long root-of-unity bins a padding position costs as much as a
-// literal in every frequency, and each doubling of L adds a butterfly stage
-// per frequency.  Fewer distinct shapes mean fewer, larger kernel launches.
-void shape_for(int ct, int k, int &seg, int &L)
+// take every SEG from 14 to 26 and 32-lane groups (k > 416) 14, 15 or 16:
+// in root-of-unity bins a padding position costs as much as a literal in
+// every frequency, and each doubling of L adds a butterfly stage per
+// frequency.  Real chains pay for padding once, so they keep the coarser
+// steps: fewer distinct shapes mean fewer, larger kernel launches.
+void shape_for(int ct, int k, int &seg, int &L, bool dft)
 {
     if (ct == CT_F64) {
         L = 1;
@@ -470,7 +472,9 @@ void shape_for(int ct, int k, int &seg, int &L)
         return;
     }
     // FP32: segments of at most 24 literals (the register budget of 3+ waves
-    // per SIMD), 32 only where 16 lanes of 24 do not reach (k > 384)
+    // per SIMD), 32 only where 16 lanes of 24 do not reach (k > 384); counts
+    // in steps of 4 on one lane, 16, 20 or 24 on several for root-of-unity
+    // products
     int smax = 24;
     L = 1;
     while ((k + L - 1) / L > smax) {
@@ -482,8 +486,11 @@ void shape_for(int ct, int k, int &seg, int &L)
     }
     const int s = (k + L - 1) / L;
     if (s <= 4) seg = 4;
-    else if (s <= 8) seg = 8;
-    else seg = ((s + 7) / 8) * 8;   // 16, 24 (32 only past k = 384)
+    else if (!dft) seg = s <= 8 ? 8 : ((s + 7) / 8) * 8;   // 8, 16, 24 (32)
+    else if (L == 1) seg = ((s + 3) / 4) * 4;   // 8, 12, ..., 24
+    else if (s <= 16) seg = 16;
+    else if (s <= 20) seg = 20;
+    else seg = ((s + 7) / 8) * 8;   // 24 (32 only past k = 384)
 }
 
 struct TypeKey {
@@ -715,7 +722,7 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
         else ct = (cls == CLASS_DFT && k >= p->fp64_min_len) ? CT_F64 : CT_F32;
         int seg, L;
         if (uc && cls == CLASS_DFT) shape_for_uc(k, seg, L);
-        else shape_for(ct, k, seg, L);
+        else shape_for(ct, k, seg, L, cls == CLASS_DFT);
         if (!eval_variant_exists(io, ct, cls, seg, L, uc))
             return fail(FFSAT_E_UNSUPPORTED, "no kernel variant for constraint %d (k=%d)", c, k);
         TypeKey tk;
