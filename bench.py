@@ -16,11 +16,14 @@ objective are produced.
 
 `roofline` describes the kernel with the most time per step, timed live
 with HIP events on the stream it runs on.  One convention throughout:
-root-of-unity kernels are priced at 10 k^2 FLOP per (constraint, restart)
-against the published vector peak of their arithmetic type (FP32 157.3,
-FP64 78.6 TFLOP/s) -- the kernels' own count, about 7 k^2 (14 FLOP per
-literal and complex frequency over floor(k/2) frequencies), is reported
-beside it as flop_exact_per_launch / frac_exact; transform-free chains and
+FP32 root-of-unity kernels (running products) are priced at 10 k^2 FLOP per
+(constraint, restart) against the published vector peak of their
+arithmetic type (FP32 157.3, FP64 78.6 TFLOP/s) -- the kernels' own count,
+about 7 k^2 (14 FLOP per literal and complex frequency over floor(k/2)
+frequencies), is reported beside it as flop_exact_per_launch / frac_exact;
+FP64 root-of-unity kernels (the polynomial form, about 2.25 k^2 + O(k) per
+frequency-independent part) at that form's own FLOP count, from the
+library's bin description (both figures then agree); transform-free chains and
 the reduction move 8 B per (literal, restart) in the evaluation (a gathered
 point, a slot written) plus 4 B per (literal, restart) and 8 B per
 (variable, restart) in the reduction; the pulled gradient moves 4 B per
@@ -110,8 +113,12 @@ def parse():
 # ----------------------------------------------------------------------------- roofline
 
 def bin_work(bd, B):
-    """Algorithmic work of one evaluation bin per launch: (flop, bytes, dtype)."""
-    flop = FLOP_PER_K2 * bd.get("k2_per_restart", 0.0) * B
+    """Algorithmic work of one evaluation bin per launch: (flop, bytes, dtype).
+    Root-of-unity bins: the library's per-restart figure (10 k^2 per
+    constraint for the running-product form, the polynomial form's own count
+    for FP64 bins), else 10 k^2."""
+    per = bd.get("alg_flops_per_restart")
+    flop = (per if per is not None else FLOP_PER_K2 * bd.get("k2_per_restart", 0.0)) * B
     nbytes = 8.0 * bd["lits"] * B
     return flop, nbytes, bd["ct"]
 

@@ -390,6 +390,152 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
     }
 }
 
+// ---- FP64 root-of-unity products in the polynomial form
+//
+// A lane's segment product of form-1 factors, init * prod_t (1 - i tau l_t),
+// is init * sum_m e_m z^m at z = -i tau, e_m the elementary symmetric
+// polynomials of the segment's literals: they do not depend on the
+// frequency, so the lane forms them once per constraint and each frequency
+// evaluates two real polynomials in sg = z^2 = -tau^2 (Horner), about SEG
+// FP64 operations instead of 3 SEG for the running product.  The leave-one-out
+// product of position t is init * sum_m e^(-t)_m z^m (e^(-t): the elementary
+// symmetric polynomials of the other positions), so each position's gradient,
+// sum over frequencies of Re(C z^m) e^(-t)_m with C = c1 * (product of the
+// other lanes) * init, only needs the moments H_m = sum_f Re(C_f z_f^m): 1.5
+// operations per position and frequency; the positions' gradients follow
+// from H once per constraint (seg_grad_from_moments).  Rounding: every
+// quantity is a sum of products of nonnegative weights (the polynomials of
+// |l|) with the exact terms, so the error of a frequency's contribution is
+// within about SEG eps prod_t (1 + |tau l_t|) <= SEG eps 2^(SEG/2) |prod_t
+// (1 - i tau l_t)|: below 1e-9 relative for SEG <= 32 in FP64 (not in FP32,
+// which keeps the running products).
+
+// e[0..SEG]: elementary symmetric polynomials of v[0..SEG-1]
+template <int SEG>
+__device__ __forceinline__ void seg_esp(const double (&v)[SEG], double (&e)[SEG + 1])
+{
+    e[0] = 1.0;
+#pragma unroll
+    for (int m = 1; m <= SEG; ++m) e[m] = 0.0;
+#pragma unroll
+    for (int t = 0; t < SEG; ++t) {
+#pragma unroll
+        for (int m = SEG; m >= 1; --m)
+            if (m <= t + 1) e[m] = fmaT(v[t], e[m - 1], e[m]);
+    }
+}
+
+// One frequency: value term Re(c0 T) into we (T: the product over the
+// group's L lanes) and the moments H_m += Re(c1 (T / P) init z^m), P this
+// lane's segment product.
+template <int SEG, int L>
+__device__ __forceinline__ void freq_pass_poly(const double (&e)[SEG + 1], double (&H)[SEG],
+                                               const FreqT<double> &fr, double &we)
+{
+    const double tau = fr.tk;
+    const double sg = -tau * tau;
+    constexpr int NE = SEG / 2;         // highest even degree 2 NE <= SEG
+    constexpr int NO = (SEG - 1) / 2;   // highest odd degree 2 NO + 1 <= SEG
+    double A = e[2 * NE];
+#pragma unroll
+    for (int n = NE - 1; n >= 0; --n) A = fmaT(A, sg, e[2 * n]);
+    double Bo = e[2 * NO + 1];
+#pragma unroll
+    for (int n = NO - 1; n >= 0; --n) Bo = fmaT(Bo, sg, e[2 * n + 1]);
+    const double itau = fr.init * tau;
+    const double Pr = fr.init * A;   // P = init (A - i tau B)
+    const double Pi = -itau * Bo;
+    double Tr = Pr, Ti = Pi;
+    allreduce_prod_f64<L>(Tr, Ti);
+    we += fmaT(fr.c0re, Tr, -fr.c0im * Ti);
+    double qr = 1.0, qi = 0.0;   // T / P: the other lanes' product
+    if constexpr (L >= 2) {
+        const double nrm = fmaT(Pr, Pr, Pi * Pi);
+        const double rinv = recip_f64(nrm);
+        const double ir = Pr * rinv, ii = -Pi * rinv;
+        qr = fmaT(Tr, ir, -Ti * ii);
+        qi = fmaT(Tr, ii, Ti * ir);
+    }
+    // C = c1 q init: Re(C z^(2n)) = sg^n Re(C), Re(C z^(2n+1)) = sg^n tau Im(C)
+    const double Cr = fr.init * fmaT(fr.c1re, qr, -fr.c1im * qi);
+    const double Ci = itau * fmaT(fr.c1re, qi, fr.c1im * qr);
+    double pw = 1.0;
+#pragma unroll
+    for (int n = 0; 2 * n < SEG; ++n) {
+        H[2 * n] = fmaT(pw, Cr, H[2 * n]);
+        if (2 * n + 1 < SEG) H[2 * n + 1] = fmaT(pw, Ci, H[2 * n + 1]);
+        if (2 * n + 2 < SEG) pw *= sg;
+    }
+}
+
+// out(t, sum_m e^(-t)_m H_m) for every position t of the segment.  Blocks of
+// GB positions: O = polynomials of the positions outside the block, K_a =
+// sum_c O_c H_(a+c), then gr[t] = sum_a E^(t)_a K_a with E^(t) the
+// polynomials of the block's other positions (no division, so no
+// cancellation beyond the bound above).  About 3 SEG^2 operations, once per
+// constraint.
+template <int SEG, typename V, typename Out>
+__device__ __forceinline__ void seg_grad_from_moments(V (&v)[SEG], double (&H)[SEG], Out &&out)
+{
+    // every loop has a constant trip count with the bounds as conditions in
+    // the body, so that full unrolling never leaves an indexed array behind
+    constexpr int GB = 8;
+#pragma unroll
+    for (int lo = 0; lo < SEG; lo += GB) {
+        const int nb = lo + GB <= SEG ? GB : SEG - lo;
+        // one block at a time: opaque inputs keep the scheduler from
+        // interleaving the blocks (each holds its own O, K and E)
+#pragma unroll
+        for (int u = 0; u < SEG; ++u) asm volatile("" : "+v"(v[u]), "+v"(H[u]));
+        double O[SEG + 1];
+        O[0] = 1.0;
+#pragma unroll
+        for (int m = 1; m <= SEG; ++m) O[m] = 0.0;
+#pragma unroll
+        for (int u = 0; u < SEG; ++u) {
+            if (u >= lo && u < lo + nb) continue;
+            const int deg = u < lo ? u + 1 : u + 1 - nb;
+            const double vu = (double)v[u];
+#pragma unroll
+            for (int m = SEG; m >= 1; --m)
+                if (m <= deg) O[m] = fmaT(vu, O[m - 1], O[m]);
+        }
+        double K[GB];
+#pragma unroll
+        for (int a2 = 0; a2 < GB; ++a2) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c <= SEG; ++c)
+                if (a2 < nb && c + nb <= SEG) acc = fmaT(O[c], H[a2 + c < SEG ? a2 + c : 0], acc);
+            K[a2] = acc;
+        }
+#pragma unroll
+        for (int t = 0; t < GB; ++t) {
+            if (t < nb) {
+                double E[GB];
+                E[0] = 1.0;
+#pragma unroll
+                for (int m = 1; m < GB; ++m) E[m] = 0.0;
+#pragma unroll
+                for (int u = 0; u < GB; ++u) {
+                    if (u < nb && u != t) {
+                        const int deg = u < t ? u + 1 : u;   // positions of the block before u, t excluded
+                        const double vu = (double)v[lo + u < SEG ? lo + u : 0];
+#pragma unroll
+                        for (int m = GB - 1; m >= 1; --m)
+                            if (m <= deg) E[m] = fmaT(vu, E[m - 1], E[m]);
+                    }
+                }
+                double g = 0.0;
+#pragma unroll
+                for (int a2 = 0; a2 < GB; ++a2)
+                    if (a2 < nb) g = fmaT(E[a2], K[a2], g);
+                out(lo + t, g);
+            }
+        }
+    }
+}
+
 // First frequency of wave w of fg that split a constraint's n1 form-1 and
 // nf - n1 form-2 frequencies (and the real chain, on the last wave) into
 // shares of about equal estimated VALU work.  Wave-uniform integer arithmetic.
@@ -401,6 +547,38 @@ __device__ __forceinline__ int freq_bound(int w, int fg, int n1, int nf, int has
     const int tgt = (total * w + fg / 2) / fg;
     const int f = tgt <= 4 * n1 ? (tgt + 3) / 4 : n1 + (tgt - 4 * n1 + 4) / 5;
     return min(f, nf);
+}
+
+// Partial sums of the fg waves of a workgroup that split a constraint's
+// frequencies (v[] and we), added in wave order by wave 0.  One base index
+// per wave, positions at constant offsets; the index (not the pointer, which
+// must stay an LDS pointer) is opaque so that the compiler does not hoist SEG
+// addresses.
+template <typename CT, int SEG>
+__device__ __forceinline__ void waves_reduce(void *lds, int wg, int fg, int lane, CT (&v)[SEG], CT &we)
+{
+    CT *red = reinterpret_cast<CT *>(lds);
+    if (wg > 0) {
+        int base = (wg - 1) * (SEG + 1) * 64 + lane;
+        asm volatile("" : "+v"(base));
+#pragma unroll
+        for (int t = 0; t < SEG; ++t) red[base + t * 64] = v[t];
+        red[base + SEG * 64] = we;
+    }
+    __syncthreads();
+    if (wg == 0) {
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+            if (q < fg) {
+                int base = (q - 1) * (SEG + 1) * 64 + lane;
+                asm volatile("" : "+v"(base));
+#pragma unroll
+                for (int t = 0; t < SEG; ++t) v[t] += red[base + t * 64];
+                we += red[base + SEG * 64];
+            }
+        }
+    }
+    __syncthreads();   // the next constraint reuses the buffer
 }
 
 // The work of one wave: unit = (chunk of sp.cpw constraints of the range
@@ -423,6 +601,8 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
 {
     const int fg = CPLX ? fg_in : 1;
     const int wg = CPLX ? wg_in : 0;
+    // FP64 root-of-unity bins take the polynomial form (seg_esp / freq_pass_poly)
+    constexpr bool POLY = CPLX && !UC && sizeof(CT) == 8 && SEG <= 32;
     constexpr int RPW = 64 / L;
     const int lane = threadIdx.x & 63;
     const int n_chunks = (sp.count + sp.cpw - 1) / sp.cpw;
@@ -497,93 +677,126 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
         if (!a.do_value) continue;
 
         CT gr[SEG];
-#pragma unroll
-        for (int t = 0; t < SEG; ++t) {
-            gr[t] = 0;
-            // materialised here, once: keeps one register set for the
-            // accumulators across both frequency loops (no bypass copies)
-            if constexpr (CPLX) asm volatile("" : "+v"(gr[t]));
-        }
         CT we = 0;
-        if constexpr (CPLX && UC) {
-            const int nf = ty.n1;
-            const int f0 = (nf * wg) / fg, f1 = (nf * (wg + 1)) / fg;
-            FreqT<CT> fr = freqs[ty.tab + f0];
-#pragma unroll 1
-            for (int f = f0; f < f1; ++f) {
-                const FreqT<CT> nxt = freqs[ty.tab + f + 1];
-                freq_pass<CT, SEG, L, 3>(j, lv, gr, fr, we);
-                fr = nxt;
+        if constexpr (POLY) {
+            // FP64 root-of-unity products in the polynomial form: moments of
+            // every frequency, then the positions' gradients from them
+            double e[SEG + 1];
+            seg_esp<SEG>(lv, e);
+            // the literals again for the gradients, in the input type (exact:
+            // +-x or the padding 1), so that the FP64 copies die here
+            IO lio[SEG];
+#pragma unroll
+            for (int t = 0; t < SEG; ++t) {
+                lio[t] = (IO)lv[t];
+                asm volatile("" : "+v"(lio[t]));   // materialised: not re-derived from lv later
             }
-        } else if constexpr (CPLX) {
+            double H[SEG];
+#pragma unroll
+            for (int t = 0; t < SEG; ++t) {
+                H[t] = 0;
+                asm volatile("" : "+v"(H[t]));
+            }
             const int n1 = ty.n1, nf = ty.n1 + ty.n2;
-            // this wave's frequencies: equal shares of the estimated work
-            // (4 units per form-1 frequency, 5 per form-2 one, 4 for the real
-            // chain, which the last wave takes)
             const int f0 = freq_bound(wg, fg, n1, nf, ty.has_real);
             const int f1 = freq_bound(wg + 1, fg, n1, nf, ty.has_real);
             FreqT<CT> fr = freqs[ty.tab + f0];
 #pragma unroll 1
-            for (int f = f0; f < min(f1, n1); ++f) {
+            for (int f = f0; f < f1; ++f) {
                 const FreqT<CT> nxt = freqs[ty.tab + f + 1];   // table has one entry of padding
-                freq_pass<CT, SEG, L, 1>(j, lv, gr, fr, we);
+                freq_pass_poly<SEG, L>(e, H, fr, we);
                 fr = nxt;
             }
-#pragma unroll 1
-            for (int f = max(f0, n1); f < f1; ++f) {
-                const FreqT<CT> nxt = freqs[ty.tab + f + 1];
-                freq_pass<CT, SEG, L, 2>(j, lv, gr, fr, we);
-                fr = nxt;
+            if (ty.has_real && wg == fg - 1) {
+                // the chain prod l of the root z = -1 (alpha = 0, beta = 1;
+                // padding factors 1): its segment product is e_SEG and the
+                // leave-one-out products inside the segment are e^(-t)_(SEG-1)
+                CT pre, suf;
+                group_scan_real<CT, L>(j, e[SEG], pre, suf);
+                we += ty.c0r * (e[SEG] * suf);
+                H[SEG - 1] = fmaT(ty.c1r, pre * suf, H[SEG - 1]);
             }
-        }
-        if (ty.has_real && wg == fg - 1) {
-            // real chain: prod (alpha + beta l); padding factors are exactly 1
-            CT q[SEG];
-            CT P = 1;
+            if (fg > 1) {
+                waves_reduce<CT, SEG>(lds, wg, fg, lane, H, we);
+                if (wg > 0) continue;
+            }
+            we += ty.cst;
+            const CT wc = (CT)wts[d.orig];
+            if (j == 0) facc = fmaT(wc, we, facc);
+            if (a.con_val != nullptr && j == 0 && bok) a.con_val[(size_t)d.orig * a.B + b] = (IO)we;
+            if (a.want_grad && bok) {
+                asm volatile("" : "+v"(nv));
+                seg_grad_from_moments<SEG>(lio, H, [&](int t, double g) {
+                    if (t < nv) {
+                        const CT gv = ((negm >> t) & 1u) ? -g : g;
+                        a.slot[(size_t)(d.off + i0 + t) * a.B + b] = (IO)(wc * gv);
+                    }
+                });
+            }
+            continue;
+        } else {
 #pragma unroll
             for (int t = 0; t < SEG; ++t) {
-                q[t] = P;
-                P = P * fmaT(ty.beta, lv[t], ty.alpha);
+                gr[t] = 0;
+                // materialised here, once: keeps one register set for the
+                // accumulators across both frequency loops (no bypass copies)
+                if constexpr (CPLX) asm volatile("" : "+v"(gr[t]));
             }
-            CT pre, suf;
-            group_scan_real<CT, L>(j, P, pre, suf);
-            we += ty.c0r * (P * suf);
-            CT S = ty.c1r * (pre * suf);
-#pragma unroll
-            for (int t = SEG - 1; t >= 0; --t) {
-                gr[t] = fmaT(q[t], S, gr[t]);
-                if (t > 0) S = S * fmaT(ty.beta, lv[t], ty.alpha);
+            if constexpr (CPLX && UC) {
+                const int nf = ty.n1;
+                const int f0 = (nf * wg) / fg, f1 = (nf * (wg + 1)) / fg;
+                FreqT<CT> fr = freqs[ty.tab + f0];
+#pragma unroll 1
+                for (int f = f0; f < f1; ++f) {
+                    const FreqT<CT> nxt = freqs[ty.tab + f + 1];
+                    freq_pass<CT, SEG, L, 3>(j, lv, gr, fr, we);
+                    fr = nxt;
+                }
+            } else if constexpr (CPLX) {
+                const int n1 = ty.n1, nf = ty.n1 + ty.n2;
+                // this wave's frequencies: equal shares of the estimated work
+                // (4 units per form-1 frequency, 5 per form-2 one, 4 for the real
+                // chain, which the last wave takes)
+                const int f0 = freq_bound(wg, fg, n1, nf, ty.has_real);
+                const int f1 = freq_bound(wg + 1, fg, n1, nf, ty.has_real);
+                FreqT<CT> fr = freqs[ty.tab + f0];
+#pragma unroll 1
+                for (int f = f0; f < min(f1, n1); ++f) {
+                    const FreqT<CT> nxt = freqs[ty.tab + f + 1];   // table has one entry of padding
+                    freq_pass<CT, SEG, L, 1>(j, lv, gr, fr, we);
+                    fr = nxt;
+                }
+#pragma unroll 1
+                for (int f = max(f0, n1); f < f1; ++f) {
+                    const FreqT<CT> nxt = freqs[ty.tab + f + 1];
+                    freq_pass<CT, SEG, L, 2>(j, lv, gr, fr, we);
+                    fr = nxt;
+                }
             }
-        }
-        if constexpr (CPLX) {
-            if (fg > 1) {
-                // partial sums of the fg waves, added in wave order by wave 0
-                // one base index per wave, positions at constant offsets; the
-                // index (not the pointer, which must stay an LDS pointer) is
-                // opaque so that the compiler does not hoist SEG addresses
-                CT *red = reinterpret_cast<CT *>(lds);
-                if (wg > 0) {
-                    int base = (wg - 1) * (SEG + 1) * 64 + lane;
-                    asm volatile("" : "+v"(base));
+            if (ty.has_real && wg == fg - 1) {
+                // real chain: prod (alpha + beta l); padding factors are exactly 1
+                CT q[SEG];
+                CT P = 1;
 #pragma unroll
-                    for (int t = 0; t < SEG; ++t) red[base + t * 64] = gr[t];
-                    red[base + SEG * 64] = we;
+                for (int t = 0; t < SEG; ++t) {
+                    q[t] = P;
+                    P = P * fmaT(ty.beta, lv[t], ty.alpha);
                 }
-                __syncthreads();
-                if (wg == 0) {
+                CT pre, suf;
+                group_scan_real<CT, L>(j, P, pre, suf);
+                we += ty.c0r * (P * suf);
+                CT S = ty.c1r * (pre * suf);
 #pragma unroll
-                    for (int q = 1; q < 4; ++q) {
-                        if (q < fg) {
-                            int base = (q - 1) * (SEG + 1) * 64 + lane;
-                            asm volatile("" : "+v"(base));
-#pragma unroll
-                            for (int t = 0; t < SEG; ++t) gr[t] += red[base + t * 64];
-                            we += red[base + SEG * 64];
-                        }
-                    }
+                for (int t = SEG - 1; t >= 0; --t) {
+                    gr[t] = fmaT(q[t], S, gr[t]);
+                    if (t > 0) S = S * fmaT(ty.beta, lv[t], ty.alpha);
                 }
-                __syncthreads();   // the next constraint reuses the buffer
-                if (wg > 0) continue;
+            }
+            if constexpr (CPLX) {
+                if (fg > 1) {
+                    waves_reduce<CT, SEG>(lds, wg, fg, lane, gr, we);
+                    if (wg > 0) continue;
+                }
             }
         }
         we += ty.cst;

@@ -438,6 +438,28 @@ TypeD uc_type(const std::vector<cld> &ft, int k, int L, int s)
     return t;
 }
 
+// FLOPs (an FMA counts 2) of one restart of a root-of-unity constraint in
+// the FP64 polynomial form, as the kernel runs it on L lanes of s positions
+// with nf complex frequencies: per lane the segment's elementary symmetric
+// polynomials (s(s+1)/2 FMAs); per lane and frequency two Horner
+// evaluations (s FMAs), the segment product and the butterfly over L lanes
+// (3 + 6 log2 L), the value term (3), the quotient by the segment product
+// (16, none on one lane), the weighted coefficient (8) and the moments (s
+// FMAs, with the squared tangent and its powers: (s+1)/2 products); per
+// lane once, the gradients from the moments in blocks of 8 positions.
+double poly_flops(int s, int L, int nf)
+{
+    int lg = 0;
+    while ((1 << lg) < L) ++lg;
+    double tail = 0.0;
+    for (int lo = 0; lo < s; lo += 8) {
+        const int nb = std::min(8, s - lo), out = s - nb;
+        tail += 0.5 * out * (out + 1) + (double)nb * (out + 1) + nb * (0.5 * (nb - 1) * nb + nb);
+    }
+    const double per_freq = 4.0 * s + (s + 1) / 2 + 14.0 + (L > 1 ? 16.0 : 0.0) + 6.0 * lg;
+    return (double)L * ((double)s * (s + 1) + (double)nf * per_freq + 2.0 * tail);
+}
+
 // Segment shape of a unit-circle bin: L = 1 with SEG in {4, 8, 16}, else
 // SEG = 16 and the smallest L in 2..32 with 16 L >= k.
 void shape_for_uc(int k, int &seg, int &L)
@@ -695,7 +717,7 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
     // 1. classify every constraint into a (type, bin)
     std::map<TypeKey, int> type_index;
     std::vector<TypeD> types;
-    struct Item { int c, k, type, bin; double cost; };
+    struct Item { int c, k, type, bin; double cost, alg; };
     std::vector<Item> items((size_t)m);
     struct BinKey {
         int cls, ct, seg, L, pk;
@@ -775,24 +797,35 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
         }
         const double cost = cls == CLASS_DFT ? (double)k * (double)(types[ti].n1 + types[ti].n2 + 1) * 9.0
                                              : (double)k * 4.0;
-        items[(size_t)c] = Item{c, k, ti, bidx, cost};
         Bin &b = bins[(size_t)bidx];
-        // Algorithmic work per restart.  Per (literal, complex frequency):
-        // factor and running product 5 FLOPs, reverse product 5, leave-one-out
-        // dot 4; per frequency the step-iii dot 4.  Real chains: 8 FLOPs per
-        // literal.  Bytes: one gathered value and one slot per literal.
+        // Algorithmic work per restart.  Running products (FP32, and the
+        // unit-circle form): per (literal, complex frequency) factor and
+        // running product 5 FLOPs, reverse product 5, leave-one-out dot 4;
+        // per frequency the step-iii dot 4; real chains 8 FLOPs per literal;
+        // priced at 10 k^2 per root-of-unity constraint.  FP64 polynomial form
+        // (eval_kernel.h): its own count, poly_flops.  Bytes: one gathered
+        // value and one slot per literal.
+        double alg = 0.0;
         {
             const TypeD &td = types[(size_t)ti];
             const double nfc = (double)(td.n1 + td.n2);
-            b.flops += 14.0 * k * nfc + 4.0 * nfc + (td.has_real ? 8.0 * k : 0.0);
+            if (cls == CLASS_DFT && ct == CT_F64 && !uc) {
+                alg = poly_flops(seg, L, td.n1 + td.n2);
+                b.flops += alg;
+            } else {
+                b.flops += 14.0 * k * nfc + 4.0 * nfc + (td.has_real ? 8.0 * k : 0.0);
+                if (cls == CLASS_DFT) alg = 10.0 * (double)k * (double)k;
+            }
             b.exec_pos += (double)L * seg;
             b.bytes += (io == IO_F32 ? 8.0 : 16.0) * k;
         }
+        items[(size_t)c] = Item{c, k, ti, bidx, cost, alg};
         b.count += 1;
         b.maxk = std::max(b.maxk, k);
         b.cost += cost;
         b.lits += k;
         if (cls == CLASS_DFT) b.k2 += (double)k * (double)k;
+        b.alg += alg;
     }
 
     // 2. order bins by pull class (pullable bins last, so that their objective
@@ -826,10 +859,12 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
     Ly.cost_prefix.assign((size_t)m + 1, 0.0);
     for (int q = 0; q < m; ++q) Ly.cost_prefix[(size_t)q + 1] = Ly.cost_prefix[(size_t)q] + items[(size_t)q].cost;
     Ly.k2_prefix.assign((size_t)m + 1, 0.0);
+    Ly.alg_prefix.assign((size_t)m + 1, 0.0);
     for (int q = 0; q < m; ++q) {
         const Item &it = items[(size_t)q];
         const double k2 = bins[(size_t)it.bin].cls == CLASS_DFT ? (double)it.k * (double)it.k : 0.0;
         Ly.k2_prefix[(size_t)q + 1] = Ly.k2_prefix[(size_t)q] + k2;
+        Ly.alg_prefix[(size_t)q + 1] = Ly.alg_prefix[(size_t)q] + it.alg;
     }
 
     // 3. binned descriptors and literals, original -> binned positions
@@ -1379,7 +1414,7 @@ static hipError_t enqueue_bins(ffsat_plan *pl, int io, EvalArgs<IO> a, hipStream
 // cost-balanced contiguous constraint ranges, so that the streams can share
 // the work of one heavy bin.
 static std::vector<Bin> split_bins(const std::vector<Bin> &in, const std::vector<double> &pre,
-                                   const std::vector<double> &k2pre)
+                                   const std::vector<double> &k2pre, const std::vector<double> &algpre)
 {
     double total = 0;
     for (const Bin &b : in) total += b.cost;
@@ -1410,6 +1445,7 @@ static std::vector<Bin> split_bins(const std::vector<Bin> &in, const std::vector
             part.bytes = b.bytes * frac;
             part.exec_pos = b.exec_pos * frac;
             part.k2 = k2pre[(size_t)end] - k2pre[(size_t)start];
+            part.alg = algpre[(size_t)end] - algpre[(size_t)start];
             part.lits = (int64_t)((double)b.lits * frac);
             out.push_back(part);
             start = end;
@@ -1799,8 +1835,8 @@ extern "C" ffsat_status ffsat_plan_create(ffsat_problem *p, int32_t B, const ffs
     ffsat_plan *pl = new ffsat_plan();
     pl->p = p;
     pl->B = B;
-    pl->bins[0] = split_bins(p->lay[0].bins, p->lay[0].cost_prefix, p->lay[0].k2_prefix);
-    pl->bins[1] = split_bins(p->lay[1].bins, p->lay[1].cost_prefix, p->lay[1].k2_prefix);
+    pl->bins[0] = split_bins(p->lay[0].bins, p->lay[0].cost_prefix, p->lay[0].k2_prefix, p->lay[0].alg_prefix);
+    pl->bins[1] = split_bins(p->lay[1].bins, p->lay[1].cost_prefix, p->lay[1].k2_prefix, p->lay[1].alg_prefix);
     const int req = opts ? opts->reserved[1] : MODE_AUTO;
     if (req < MODE_AUTO || req > MODE_GROUP_DFT) {
         delete pl;
@@ -1996,7 +2032,7 @@ extern "C" ffsat_status ffsat_plan_describe(const ffsat_plan *pl, char *buf, siz
               << ", \"first\": " << b.first << ", \"count\": " << b.count << ", \"maxk\": " << b.maxk
               << ", \"lits\": " << b.lits << ", \"cost\": " << b.cost << ", \"flops_per_restart\": " << b.flops
               << ", \"bytes_per_restart\": " << b.bytes << ", \"positions_per_restart\": " << b.exec_pos
-              << ", \"k2_per_restart\": " << b.k2
+              << ", \"k2_per_restart\": " << b.k2 << ", \"alg_flops_per_restart\": " << b.alg
               << ", \"pull_class\": " << b.pk << ", \"pulled\": " << (io == IO_F32 && pl->pull && b.pk >= pl->pull ? "true" : "false")
               << ", \"cpw\": " << b.cpw
               << ", \"wpb\": " << b.wpb << ", \"fg\": " << b.fg;

@@ -63,6 +63,8 @@ struct Bin {
     double bytes = 0;           // algorithmic HBM bytes per restart (gathers + slot writes)
     double exec_pos = 0;        // literal positions executed per restart (with padding)
     double k2 = 0;              // sum of k^2 over the bin's root-of-unity constraints
+    double alg = 0;             // roofline FLOPs per restart: 10 k^2 per root-of-unity constraint,
+                                // the polynomial form's own count in FP64 (poly_flops)
     int cpw = 1, wpb = 4;       // tile shape: constraints per wave, waves per block
     int fg = 1;                 // root-of-unity bins: waves splitting one unit's frequencies
     bool uc = false;            // root-of-unity bin in the unit-circle form (ablation)
@@ -103,6 +105,7 @@ struct Layout {
     std::vector<Bin> bins;
     std::vector<double> cost_prefix;   // [m+1] prefix sums of per-constraint cost (binned order)
     std::vector<double> k2_prefix;     // [m+1] prefix sums of k^2 of root-of-unity constraints (binned order)
+    std::vector<double> alg_prefix;    // [m+1] prefix sums of the constraints' roofline FLOPs (Bin::alg)
     ConDesc *d_con = nullptr;
     int32_t *d_lit = nullptr;    // var | (negated << 31), binned order
     int32_t *d_vptr = nullptr;   // [n+1] variable -> slot CSR
