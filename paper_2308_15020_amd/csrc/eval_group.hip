@@ -68,12 +68,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 }
 
 // The long root-of-unity bins with FP64 arithmetic (k > 256 by default) in
-// one grid as well: their kernels all run at 2 waves per SIMD, so one grid
-// costs no occupancy, and the ramp and tail of a launch are paid once
-// instead of once per bin.  (SEG, L): 14..16 at L = 32, 17..26 at L = 16.
+// one grid as well: the ramp and tail of a launch are paid once instead of
+// once per bin.  (SEG, L): 17..32 at L = 16.
 #define FFSAT_GROUP64_SHAPES(X)                                                                           \
-    X(0, 14, 32) X(1, 15, 32) X(2, 16, 32) X(3, 17, 16) X(4, 18, 16) X(5, 19, 16) X(6, 20, 16)           \
-    X(7, 21, 16) X(8, 22, 16) X(9, 23, 16) X(10, 24, 16) X(11, 25, 16) X(12, 26, 16)
+    X(0, 17, 16) X(1, 18, 16) X(2, 19, 16) X(3, 20, 16) X(4, 21, 16) X(5, 22, 16) X(6, 23, 16)           \
+    X(7, 24, 16) X(8, 25, 16) X(9, 26, 16) X(10, 27, 16) X(11, 28, 16) X(12, 29, 16) X(13, 30, 16)       \
+    X(14, 31, 16) X(15, 32, 16)
 
 int group_variant64(int seg, int L)
 {

@@ -683,14 +683,6 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
             // every frequency, then the positions' gradients from them
             double e[SEG + 1];
             seg_esp<SEG>(lv, e);
-            // the literals again for the gradients, in the input type (exact:
-            // +-x or the padding 1), so that the FP64 copies die here
-            IO lio[SEG];
-#pragma unroll
-            for (int t = 0; t < SEG; ++t) {
-                lio[t] = (IO)lv[t];
-                asm volatile("" : "+v"(lio[t]));   // materialised: not re-derived from lv later
-            }
             double H[SEG];
 #pragma unroll
             for (int t = 0; t < SEG; ++t) {
@@ -726,6 +718,20 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
             if (a.con_val != nullptr && j == 0 && bok) a.con_val[(size_t)d.orig * a.B + b] = (IO)we;
             if (a.want_grad && bok) {
                 asm volatile("" : "+v"(nv));
+                // the literals again, from memory (L2): keeping them across
+                // the frequency loop would cost SEG registers there.  The
+                // opaque index keeps the compiler from reusing the first loads.
+                int ib = i0;
+                asm volatile("" : "+v"(ib));
+                int lr[SEG];
+#pragma unroll
+                for (int t = 0; t < SEG; ++t) lr[t] = lits[d.off + min(ib + t, k - 1)];
+                IO lio[SEG];
+#pragma unroll
+                for (int t = 0; t < SEG; ++t) {
+                    const IO xv = xin[(size_t)(lr[t] & 0x7fffffff) * a.B + bb];
+                    lio[t] = t < nv ? (lr[t] < 0 ? -xv : xv) : (IO)ty.pad;
+                }
                 seg_grad_from_moments<SEG>(lio, H, [&](int t, double g) {
                     if (t < nv) {
                         const CT gv = ((negm >> t) & 1u) ? -g : g;
@@ -861,10 +867,11 @@ struct EvalFn {
 // Segment shapes.  FP32 arithmetic: L = 1 with SEG in {4, 8, ..., 32}, L >= 2
 // with SEG in {16, 20, 24, 28, 32}.  FP64 arithmetic: L = 1 with SEG in
 // {4, 8, ..., 24}; L = 2..8 with SEG in {16, 20, 24}; L = 16 with every SEG
-// from 14 to 26 and L = 32 with SEG 14, 15 or 16 (the long root-of-unity
-// bins, where a padding position costs as much as a literal in every
-// frequency; 26 positions at 16 lanes still fit 2 waves per SIMD, 28 do
-// not).
+// from 14 to 32 (the long root-of-unity bins: a padding position costs as
+// much as a literal in every frequency, and in the polynomial form the
+// per-frequency cost of a lane, about 2.5 SEG operations plus a butterfly
+// stage per doubling of L, favours long segments; 32 positions still fit 2
+// waves per SIMD).
 template <typename IO, typename CT, int SEG, int L, bool CPLX>
 static EvalFn<IO> handle()
 {
@@ -882,9 +889,9 @@ static EvalFn<IO> pick_L(int seg)
     case 4: if constexpr (L == 1) return handle<IO, CT, 4, L, CPLX>(); break;
     case 8: if constexpr (L == 1) return handle<IO, CT, 8, L, CPLX>(); break;
     case 12: if constexpr (L == 1) return handle<IO, CT, 12, L, CPLX>(); break;
-    case 14: if constexpr (F64 && L >= 16) return handle<IO, CT, 14, L, CPLX>(); break;
-    case 15: if constexpr (F64 && L >= 16) return handle<IO, CT, 15, L, CPLX>(); break;
-    case 16: return handle<IO, CT, 16, L, CPLX>();
+    case 14: if constexpr (F64 && L == 16) return handle<IO, CT, 14, L, CPLX>(); break;
+    case 15: if constexpr (F64 && L == 16) return handle<IO, CT, 15, L, CPLX>(); break;
+    case 16: if constexpr (!F64 || L <= 16) return handle<IO, CT, 16, L, CPLX>(); break;
     case 17: if constexpr (F64 && L == 16) return handle<IO, CT, 17, L, CPLX>(); break;
     case 18: if constexpr (F64 && L == 16) return handle<IO, CT, 18, L, CPLX>(); break;
     case 19: if constexpr (F64 && L == 16) return handle<IO, CT, 19, L, CPLX>(); break;
@@ -895,8 +902,12 @@ static EvalFn<IO> pick_L(int seg)
     case 24: if constexpr (!F64 || L <= 16) return handle<IO, CT, 24, L, CPLX>(); break;
     case 25: if constexpr (F64 && L == 16) return handle<IO, CT, 25, L, CPLX>(); break;
     case 26: if constexpr (F64 && L == 16) return handle<IO, CT, 26, L, CPLX>(); break;
-    case 28: if constexpr (!F64) return handle<IO, CT, 28, L, CPLX>(); break;
-    case 32: if constexpr (!F64) return handle<IO, CT, 32, L, CPLX>(); break;
+    case 27: if constexpr (F64 && L == 16) return handle<IO, CT, 27, L, CPLX>(); break;
+    case 28: if constexpr (!F64 || L == 16) return handle<IO, CT, 28, L, CPLX>(); break;
+    case 29: if constexpr (F64 && L == 16) return handle<IO, CT, 29, L, CPLX>(); break;
+    case 30: if constexpr (F64 && L == 16) return handle<IO, CT, 30, L, CPLX>(); break;
+    case 31: if constexpr (F64 && L == 16) return handle<IO, CT, 31, L, CPLX>(); break;
+    case 32: if constexpr (!F64 || L == 16) return handle<IO, CT, 32, L, CPLX>(); break;
     default: break;
     }
     return EvalFn<IO>{};

@@ -474,19 +474,18 @@ void shape_for_uc(int k, int &seg, int &L)
 // SEG.  FP32 arithmetic: SEG in {4, 8, 16, 24} (32 past k = 384); products
 // at roots of unity (dft) also take 12 on one lane and 20 on several.  FP64
 // arithmetic: SEG up to 24 (multiples of 4 below 16 lanes), 16-lane groups
-// take every SEG from 14 to 26 and 32-lane groups (k > 416) 14, 15 or 16:
-// in root-of-unity bins a padding position costs as much as a literal in
-// every frequency, and each doubling of L adds a butterfly stage per
-// frequency.  Real chains pay for padding once, so they keep the coarser
+// take every SEG from 14 to 32 (k <= 512): in root-of-unity bins a padding
+// position costs as much as a literal in every frequency, and each doubling
+// of L adds a butterfly stage per frequency.  Real chains pay for padding once, so they keep the coarser
 // steps: fewer distinct shapes mean fewer, larger kernel launches.
 void shape_for(int ct, int k, int &seg, int &L, bool dft)
 {
     if (ct == CT_F64) {
         L = 1;
-        while ((k + L - 1) / L > 24 && L < 32) L <<= 1;
-        // 16 lanes of up to 26 positions before 32 lanes: a butterfly stage
-        // less per frequency and less padding (k <= 416)
-        if (L == 32 && (k + 15) / 16 <= 26) L = 16;
+        while ((k + L - 1) / L > 24 && L < 16) L <<= 1;
+        // 16 lanes of up to 32 positions (k <= 512); longer constraints have
+        // no FP64 variant (32 lanes)
+        if (L == 16 && (k + 15) / 16 > 32) L = 32;
         const int s = (k + L - 1) / L;
         if (L >= 16) seg = std::max(14, s);   // every count: padding costs as much as a literal
         else if (L > 1) seg = std::max(16, ((s + 3) / 4) * 4);
