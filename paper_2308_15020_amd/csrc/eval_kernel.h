@@ -427,13 +427,13 @@ __device__ __forceinline__ void seg_esp(const double (&v)[SEG], double (&e)[SEG 
 
 // One frequency: value term Re(c0 T) into we (T: the product over the
 // group's L lanes) and the moments H_m += Re(c1 (T / P) init z^m), P this
-// lane's segment product.
+// lane's segment product.  With W = c1 init T / P and c0 = i c1 / tau,
+// Re(c0 T) = Re(W (A - i tau B) i / tau) = B Re(W) + A tau Im(W) / sg.
 template <int SEG, int L>
-__device__ __forceinline__ void freq_pass_poly(const double (&e)[SEG + 1], double (&H)[SEG],
-                                               const FreqT<double> &fr, double &we)
+__device__ __forceinline__ void freq_pass_poly(const double (&e)[SEG + 1], double (&H)[SEG], const FreqPoly &fr,
+                                               double &we)
 {
-    const double tau = fr.tk;
-    const double sg = -tau * tau;
+    const double sg = fr.sg;
     constexpr int NE = SEG / 2;         // highest even degree 2 NE <= SEG
     constexpr int NO = (SEG - 1) / 2;   // highest odd degree 2 NO + 1 <= SEG
     double A = e[2 * NE];
@@ -442,23 +442,23 @@ __device__ __forceinline__ void freq_pass_poly(const double (&e)[SEG + 1], doubl
     double Bo = e[2 * NO + 1];
 #pragma unroll
     for (int n = NO - 1; n >= 0; --n) Bo = fmaT(Bo, sg, e[2 * n + 1]);
-    const double itau = fr.init * tau;
     const double Pr = fr.init * A;   // P = init (A - i tau B)
-    const double Pi = -itau * Bo;
-    double Tr = Pr, Ti = Pi;
-    allreduce_prod_f64<L>(Tr, Ti);
-    we += fmaT(fr.c0re, Tr, -fr.c0im * Ti);
-    double qr = 1.0, qi = 0.0;   // T / P: the other lanes' product
+    const double Pi = -fr.itau * Bo;
+    double qr = 1.0, qi = 0.0;       // T / P: the other lanes' product
     if constexpr (L >= 2) {
+        double Tr = Pr, Ti = Pi;
+        allreduce_prod_f64<L>(Tr, Ti);
         const double nrm = fmaT(Pr, Pr, Pi * Pi);
         const double rinv = recip_f64(nrm);
         const double ir = Pr * rinv, ii = -Pi * rinv;
         qr = fmaT(Tr, ir, -Ti * ii);
         qi = fmaT(Tr, ii, Ti * ir);
     }
-    // C = c1 q init: Re(C z^(2n)) = sg^n Re(C), Re(C z^(2n+1)) = sg^n tau Im(C)
-    const double Cr = fr.init * fmaT(fr.c1re, qr, -fr.c1im * qi);
-    const double Ci = itau * fmaT(fr.c1re, qi, fr.c1im * qr);
+    // Re(W) and tau Im(W); Re(W z^(2n)) = sg^n Re(W), Re(W z^(2n+1)) = sg^n tau Im(W)
+    const double Cr = fmaT(fr.c1ire, qr, -fr.c1iim * qi);
+    const double Ci = fmaT(fr.c1tre, qi, fr.c1tim * qr);
+    we = fmaT(Cr, Bo, we);
+    we = fmaT(Ci * fr.isg, A, we);
     double pw = 1.0;
 #pragma unroll
     for (int n = 0; 2 * n < SEG; ++n) {
@@ -692,13 +692,18 @@ __device__ __forceinline__ void eval_unit(const EvalArgs<IO> &a, const Span sp, 
             const int n1 = ty.n1, nf = ty.n1 + ty.n2;
             const int f0 = freq_bound(wg, fg, n1, nf, ty.has_real);
             const int f1 = freq_bound(wg + 1, fg, n1, nf, ty.has_real);
-            FreqT<CT> fr = freqs[ty.tab + f0];
+            // two frequencies per iteration: their Horner chains, butterflies
+            // and divisions interleave (a loop with cross-lane moves is not
+            // unrolled by the compiler), one wait for both coefficient loads
+            const FreqPoly *fp = reinterpret_cast<const FreqPoly *>(freqs) + ty.tab;
+            int f = f0;
 #pragma unroll 1
-            for (int f = f0; f < f1; ++f) {
-                const FreqT<CT> nxt = freqs[ty.tab + f + 1];   // table has one entry of padding
-                freq_pass_poly<SEG, L>(e, H, fr, we);
-                fr = nxt;
+            for (; f + 1 < f1; f += 2) {
+                const FreqPoly fa = fp[f], fb = fp[f + 1];
+                freq_pass_poly<SEG, L>(e, H, fa, we);
+                freq_pass_poly<SEG, L>(e, H, fb, we);
             }
+            if (f < f1) freq_pass_poly<SEG, L>(e, H, fp[f], we);
             if (ty.has_real && wg == fg - 1) {
                 // the chain prod l of the root z = -1 (alpha = 0, beta = 1;
                 // padding factors 1): its segment product is e_SEG and the

@@ -125,6 +125,7 @@ struct TypeD {
     double cst = 0, alpha = 0, beta = 0, c0r = 0, c1r = 0, pad = 1;
     int has_real = 0;
     int n1 = 0, n2 = 0;
+    bool poly = false;   // FP64 root-of-unity type: its FP64 table takes the FreqPoly layout
     std::vector<FreqD> fr;
 };
 
@@ -169,6 +170,7 @@ TypeD dft_type(const std::vector<cld> &hv, int k, int L, int s, bool f64)
 {
     TypeD t;
     t.cls = CLASS_DFT;
+    t.poly = f64;
     const int N = k + 1;
     const int npad = L * s - k;
     t.cst = (double)hv[0].real();
@@ -442,11 +444,11 @@ TypeD uc_type(const std::vector<cld> &ft, int k, int L, int s)
 // the FP64 polynomial form, as the kernel runs it on L lanes of s positions
 // with nf complex frequencies: per lane the segment's elementary symmetric
 // polynomials (s(s+1)/2 FMAs); per lane and frequency two Horner
-// evaluations (s FMAs), the segment product and the butterfly over L lanes
-// (3 + 6 log2 L), the value term (3), the quotient by the segment product
-// (16, none on one lane), the weighted coefficient (8) and the moments (s
-// FMAs, with the squared tangent and its powers: (s+1)/2 products); per
-// lane once, the gradients from the moments in blocks of 8 positions.
+// evaluations (s FMAs), the segment product (2) and the butterfly over L
+// lanes (6 log2 L), the quotient by the segment product (16, none on one
+// lane), the moments' coefficients (6) and the value term (5), and the
+// moments (s FMAs and (s+1)/2 - 1 powers of -tau^2); per lane once, the
+// gradients from the moments in blocks of 8 positions.
 double poly_flops(int s, int L, int nf)
 {
     int lg = 0;
@@ -456,7 +458,7 @@ double poly_flops(int s, int L, int nf)
         const int nb = std::min(8, s - lo), out = s - nb;
         tail += 0.5 * out * (out + 1) + (double)nb * (out + 1) + nb * (0.5 * (nb - 1) * nb + nb);
     }
-    const double per_freq = 4.0 * s + (s + 1) / 2 + 14.0 + (L > 1 ? 16.0 : 0.0) + 6.0 * lg;
+    const double per_freq = 4.0 * s + (s + 1) / 2 - 1 + 13.0 + (L > 1 ? 16.0 : 0.0) + 6.0 * lg;
     return (double)L * ((double)s * (s + 1) + (double)nf * per_freq + 2.0 * tail);
 }
 
@@ -909,7 +911,14 @@ static ffsat_status build_layout(ffsat_problem *p, const ffsat_problem_desc *d, 
         for (const FreqD &f : td.fr) {
             f32.push_back(FreqF32{(float)f.tk, (float)f.init, (float)f.c0re, (float)f.c0im,
                                   (float)f.c1re, (float)f.c1im, (float)f.p0, 0.f});
-            f64.push_back(FreqF64{f.tk, f.init, f.c0re, f.c0im, f.c1re, f.c1im, f.p0, 0.0});
+            if (td.poly) {
+                // FreqPoly layout (the kernel reads the entry through that type)
+                const double sg = -(f.tk * f.tk), itau = f.init * f.tk;
+                f64.push_back(FreqF64{sg, 1.0 / sg, f.init, itau, f.c1re * f.init, f.c1im * f.init,
+                                      f.c1re * itau, f.c1im * itau});
+            } else {
+                f64.push_back(FreqF64{f.tk, f.init, f.c0re, f.c0im, f.c1re, f.c1im, f.p0, 0.0});
+            }
         }
     }
     // one entry of padding: the kernels prefetch the entry after a type's last

@@ -36,6 +36,15 @@ template <typename T>
 struct FreqT {
     T tk, init, c0re, c0im, c1re, c1im, p0, p1;
 };
+// The same entry for the FP64 polynomial form (root-of-unity types with FP64
+// arithmetic, unit-circle form excepted): with tau = tk, sg = -tau^2,
+// isg = 1 / sg, itau = init tau, c1i = c1 init, c1t = c1 init tau.  The value
+// coefficient c0 = i c1 / tau is not needed: Re(c0 T) follows from the
+// moments' coefficients and the segment polynomial.
+struct FreqPoly {
+    double sg, isg, init, itau, c1ire, c1iim, c1tre, c1tim;
+};
+static_assert(sizeof(FreqPoly) == sizeof(FreqT<double>), "one table for both layouts");
 using TypeF32 = TypeT<float>;
 using TypeF64 = TypeT<double>;
 using FreqF32 = FreqT<float>;
