@@ -3,7 +3,8 @@
 Headline workload: the large hybrid instance (n = 100000 variables; 420000
 random 3-SAT clauses, 10000 XOR constraints of length 8..64, 2000
 at-least-t constraints of length 128..512), 256 restarts, FP32 with FP64
-root-of-unity products for constraints longer than 256 literals, seeded
+root-of-unity products for constraints of 128 literals or more (the
+library's default; at least those beyond 256 literals must be FP64), seeded
 synthetic data.  One step is one pass of the whole per-batch hot path:
 objective and gradient of every constraint at every restart, the
 deterministic reduction into the gradient, the projected step, the exact
@@ -65,7 +66,7 @@ FLOP_PER_K2 = 10.0                             # root-of-unity work per (constra
 WORKLOADS = {
     "large": {"gen": "config3", "seed": 3000, "B": 256, "steps": 30, "warmup": 3,
               "desc": "large hybrid SAT n=100000: 420000 3-SAT, 10000 XOR (len 8-64), 2000 at-least-t "
-                      "(len 128-512, t ~ U{{1..len/2}}; FP64 root-of-unity products beyond 256 literals), "
+                      "(len 128-512, t ~ U{{1..len/2}}; FP64 root-of-unity products from 128 literals), "
                       "{B} restarts, FP32"},
     "mixed2000": {"gen": "config2", "seed": 2000, "B": 1024, "steps": 200, "warmup": 20,
                   "desc": "mixed hybrid SAT n=2000: 8000 OR (len 3-7), 500 XOR (len 3-20), "
@@ -91,6 +92,8 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true",
                     help="measure the headline workload only")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--fp64-min-len", type=int, default=0,
+                    help="root-of-unity constraints at least this long run in FP64 (0: the library's default)")
     ap.add_argument("--eta", type=float, default=0.05)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS),
                     help="headline instance family (default: the large instance)")
@@ -183,7 +186,7 @@ def measure(name, args, dev, headline):
     B = args.restarts if (headline and args.restarts) else wl["B"]
     x_np = workloads.points(inst.n_vars, B, workloads.point_seed(wl["seed"]))
     t_setup = time.perf_counter()
-    prob = Problem(inst, device=0)
+    prob = Problem(inst, device=0, fp64_min_len=args.fp64_min_len)
     plan = Plan(prob, B, autotune=not args.no_autotune, tune_cache=args.tune_cache, side_streams=not args.serial,
                 mode=args.mode, persistent=wl.get("persistent", False))
     torch.cuda.synchronize()

@@ -94,7 +94,9 @@ typedef struct {
     int32_t device;          /* HIP device index; must be the current device */
     int32_t fp64_min_len;    /* root-of-unity products of constraints with at least
                                 this many literals run in FP64 in ffsat_eval
-                                (0 = default 257) */
+                                (0 = default 128: from there the FP64
+                                polynomial form is faster than FP32 running
+                                products, and more precise) */
     uint32_t flags;          /* FFSAT_FLAG_* */
 } ffsat_problem_desc;
 

@@ -973,7 +973,7 @@ extern "C" ffsat_status ffsat_problem_create(const ffsat_problem_desc *d, ffsat_
     p->m = d->n_cons;
     p->nnz = d->con_ptr[d->n_cons];
     p->device = d->device;
-    p->fp64_min_len = d->fp64_min_len > 0 ? d->fp64_min_len : 257;
+    p->fp64_min_len = d->fp64_min_len > 0 ? d->fp64_min_len : 128;
     p->flags = d->flags;
     for (int c = 0; c < p->m; ++c)
         p->maxk = std::max(p->maxk, (int32_t)(d->con_ptr[c + 1] - d->con_ptr[c]));

@@ -146,7 +146,7 @@ struct ffsat_problem {
     int64_t nnz = 0;
     int32_t maxk = 0;
     int32_t device = 0;
-    int32_t fp64_min_len = 257;
+    int32_t fp64_min_len = 128;
     uint32_t flags = 0;
     float *d_w = nullptr;        // weights, original order
     int32_t *d_kind = nullptr;   // original order

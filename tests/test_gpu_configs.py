@@ -113,8 +113,8 @@ def test_mixed_n2000_b1024_fused_iteration_bench_path(ffs):
 
 def test_large_n100000_b256_fused_iteration_bench_path(ffs):
     """The large instance in the benchmark's configuration (autotuned plan:
-    launch structure and pull class as the bench picks them, FP64 bins past
-    256 literals, graph-replayed fused iteration with check, projected step
+    launch structure and pull class as the bench picks them, FP64 bins from
+    128 literals, graph-replayed fused iteration with check, projected step
     and ERWA): F and the stepped point on sampled restarts against the
     oracle, satisfied counts and U over all 256 restarts bit-exact, the new
     weights against the oracle's update."""

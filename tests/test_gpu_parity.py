@@ -41,6 +41,15 @@ def _gpu_eval(plan, x, dtype=torch.float32, con=True):
     return to_np(out)
 
 
+@pytest.fixture(scope="module")
+def mixed_fp32(ffs):
+    """The same instance with FP32 root-of-unity products up to 256 literals
+    (FP64 only beyond): the FP32 kernels' long shapes."""
+    inst = every_bin_instance()
+    prob = ffs.Problem(inst, device=0, fp64_min_len=257)
+    return inst, prob
+
+
 def test_problem_bins_cover_all_variants(mixed):
     inst, prob = mixed
     info = prob.info()
@@ -58,6 +67,19 @@ def test_eval_f32_every_bin(ffs, mixed, dist, B):
     ref = oracle.eval_batch(inst, x.astype(np.float64), want_con=True)
     e = errors(inst, g, ref)
     print(dist, B, e)
+    assert e["con_val"] <= TOL32 and e["F"] <= TOL32 and e["grad"] <= TOL32, e
+
+
+@pytest.mark.parametrize("dist", ["uniform", "near_corner", "corner", "mixed_edge"])
+def test_eval_f32_long_root_of_unity_fp32(ffs, mixed_fp32, dist):
+    inst, prob = mixed_fp32
+    B = 70
+    plan = ffs.Plan(prob, B)
+    x = points(inst, B, 170, dist)
+    g = _gpu_eval(plan, x)
+    ref = oracle.eval_batch(inst, x.astype(np.float64), want_con=True)
+    e = errors(inst, g, ref)
+    print(dist, e)
     assert e["con_val"] <= TOL32 and e["F"] <= TOL32 and e["grad"] <= TOL32, e
 
 
