@@ -41,6 +41,14 @@ def trace(path: str, top: int = 25) -> str:
     lines = [f"{'kernel':<60} {'grid':>14} {'calls':>6} {'avg_us':>9} {'total_us':>10} {'share':>6}"]
     for (k, g), (n, t) in sorted(acc.items(), key=lambda kv: -kv[1][1])[:top]:
         lines.append(f"{k[:60]:<60} {g:>14} {n:>6} {t / n:>9.2f} {t:>10.1f} {t / tot:>6.3f}")
+    fams = defaultdict(lambda: [0, 0.0])
+    for (k, _g), (n, t) in acc.items():
+        f = family_of(k)
+        if f is not None:
+            fams[f][0] += n
+            fams[f][1] += t
+    for f, (n, t) in fams.items():
+        lines.append(f"family {f}: {n} dispatches, average {t / n:.2f} us, total {t:.1f} us, share {t / tot:.3f}")
     return "\n".join(lines)
 
 
@@ -86,12 +94,29 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def family_of(name: str) -> str | None:
+    """The family a template belongs to (a name with `*` for its segment
+    shape), or None: the per-bin FP64 root-of-unity kernels
+    k_eval<float, double, SEG, L, true>."""
+    m = re.fullmatch(r"k_eval<float, double, \d+, \d+, true>", name)
+    return "k_eval<float, double, *, *, true>" if m else None
+
+
 def _by_template(path, counter=None):
-    """Per kernel template name: (sum of values or durations, dispatches)."""
+    """Per kernel template name, and per family (family_of): (sum of values
+    or durations, dispatches)."""
     acc = defaultdict(float)
     calls = defaultdict(set)
     for r in csv.DictReader(open(path)):
         name = short(r["Kernel_Name"])
+        fam = family_of(name)
+        if fam is not None:
+            if counter is None:
+                acc[fam] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+                calls[fam].add(r.get("Dispatch_Id", r.get("Correlation_Id", len(calls[fam]))))
+            elif r["Counter_Name"] == counter:
+                acc[fam] += float(r["Counter_Value"])
+                calls[fam].add(r["Dispatch_Id"])
         if counter is None:
             acc[name] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
             calls[name].add(r.get("Dispatch_Id", r.get("Correlation_Id", len(calls[name]))))

@@ -64,7 +64,30 @@ def test_profsum_cards(tmp_path):
     assert card["source_sha256"] == profsum.kernel_source_hash()
 
 
-@pytest.mark.parametrize("workload,kernel", [("large", "k_eval_group64"),
+def test_profsum_family_card(tmp_path):
+    """The per-bin FP64 root-of-unity kernels (one template per segment
+    shape) also get one card as a family: average over all their dispatches."""
+    from paper_2308_15020_amd import profsum
+    a = "void ffsat::k_eval<float, double, 16, 16, true>(ffsat::EvalArgs<float>)"
+    b = "void ffsat::k_eval<float, double, 32, 16, true>(ffsat::EvalArgs<float>)"
+    trace = tmp_path / "trace.csv"
+    _write(trace, ["Kernel_Name", "Grid_Size_X", "Grid_Size_Y", "Dispatch_Id", "Start_Timestamp", "End_Timestamp"],
+           [[a, 1000, 1, 1, 0, 10000], [b, 2000, 1, 2, 20000, 50000], [a, 1000, 1, 3, 60000, 70000]])
+    hdr = ["Kernel_Name", "Grid_Size", "Dispatch_Id", "Counter_Name", "Counter_Value"]
+    sq = tmp_path / "sq.csv"
+    _write(sq, hdr, [[a, 1000, 1, "SQ_INSTS_VALU", 100], [b, 2000, 2, "SQ_INSTS_VALU", 400],
+                     [a, 1000, 3, "SQ_INSTS_VALU", 100]])
+    fam = "k_eval<float, double, *, *, true>"
+    assert profsum.family_of("k_eval<float, double, 32, 16, true>") == fam
+    assert profsum.family_of("k_eval<float, float, 16, 4, false>") is None
+    out = profsum.cards(str(trace), str(sq), str(sq), str(sq), 256, [fam])
+    card = json.loads(out.split("card: ", 1)[1])
+    assert card["rocprof_dispatches"] == 3 and card["rocprof_avg_us"] == 16.67   # (10 + 30 + 10) / 3 us
+    assert card["valu_insts_per_launch"] == 200.0
+    assert "family" in profsum.trace(str(trace))
+
+
+@pytest.mark.parametrize("workload,kernel", [("large", "k_eval<float, double, *, *, true>"),
                                              ("large3sat", "k_pull<4, 4, true>"),
                                              ("mixed2000", "k_eval_group")])
 def test_committed_cards_cover_dominant_kernels(workload, kernel):
