@@ -160,12 +160,13 @@ static std::vector<float> rkind_table()
 // segment layout (value +1, count-neutral) and the power-of-two start value
 // of every segment are folded into c0 / c1 here, in long double.
 //
-// FP64 tables (f64 = true) run every frequency with form 1's factor code:
-// a form-2 factor is kappa (1 - i l / kappa), kappa = C/S, so its lane
-// multiplies by 1 - i (S/C) l starting from kappa^s times the usual start
-// value; each segment product is then exactly the form-2 one (FP64 holds
-// kappa^s, >= 1e-41 for k <= 512), and the leave-one-out products carry one
-// extra factor kappa, divided out of c1.  3 FP64 ops per factor instead of 4.
+// FP64 tables (f64 = true) run every frequency with form 1's factor (the
+// polynomial form evaluates at z = -i tau): a form-2 factor is
+// kappa (1 - i l / kappa), kappa = C/S, so its lane takes tau = S/C and
+// starts from kappa^s times the usual start value; each segment product is
+// then exactly the form-2 one (FP64 holds kappa^s, >= 1e-81 for k <= 512 and
+// s <= 32), and the leave-one-out products carry one extra factor kappa,
+// divided out of c1.
 TypeD dft_type(const std::vector<cld> &hv, int k, int L, int s, bool f64)
 {
     TypeD t;
