@@ -468,69 +468,90 @@ __device__ __forceinline__ void freq_pass_poly(const double (&e)[SEG + 1], doubl
     }
 }
 
-// out(t, sum_m e^(-t)_m H_m) for every position t of the segment.  Blocks of
-// GB positions: O = polynomials of the positions outside the block, K_a =
-// sum_c O_c H_(a+c), then gr[t] = sum_a E^(t)_a K_a with E^(t) the
-// polynomials of the block's other positions (no division, so no
-// cancellation beyond the bound above).  About 3 SEG^2 operations, once per
-// constraint.
+// out(t, sum_m e^(-t)_m H_m) for every position t of the segment, with no
+// division (no cancellation beyond the bound above).  Blocks of GB positions,
+// last block first.  R = the moments taken through the positions after the
+// block (R_q = sum_j S_j H_(q+j), S the polynomials of those positions; one
+// in-place step R_q += v_u R_(q+1) per position, so R starts as H); K_a =
+// sum_i P_i R_(a+i) with P the polynomials of the positions before the block;
+// inside the block the same once more: G = K taken through the block's
+// positions after t, and out(t, sum_i Q_i G_i), Q the polynomials of the
+// block's positions before t.  About 2 SEG^2 FMAs per lane (SEG = 32), once
+// per constraint.  H is overwritten.
 template <int SEG, typename V, typename Out>
 __device__ __forceinline__ void seg_grad_from_moments(V (&v)[SEG], double (&H)[SEG], Out &&out)
 {
     // every loop has a constant trip count with the bounds as conditions in
     // the body, so that full unrolling never leaves an indexed array behind
     constexpr int GB = 8;
+    constexpr int NBLK = (SEG + GB - 1) / GB;
 #pragma unroll
-    for (int lo = 0; lo < SEG; lo += GB) {
+    for (int bi = NBLK - 1; bi >= 0; --bi) {
+        const int lo = bi * GB;
         const int nb = lo + GB <= SEG ? GB : SEG - lo;
+        const int hi = lo + nb;
         // one block at a time: opaque inputs keep the scheduler from
-        // interleaving the blocks (each holds its own O, K and E)
+        // interleaving the blocks (each holds its own P, K and G)
 #pragma unroll
         for (int u = 0; u < SEG; ++u) asm volatile("" : "+v"(v[u]), "+v"(H[u]));
-        double O[SEG + 1];
-        O[0] = 1.0;
+        double P[SEG + 1];
+        P[0] = 1.0;
 #pragma unroll
-        for (int m = 1; m <= SEG; ++m) O[m] = 0.0;
+        for (int m = 1; m <= SEG; ++m) P[m] = 0.0;
 #pragma unroll
         for (int u = 0; u < SEG; ++u) {
-            if (u >= lo && u < lo + nb) continue;
-            const int deg = u < lo ? u + 1 : u + 1 - nb;
-            const double vu = (double)v[u];
+            if (u < lo) {
+                const double vu = (double)v[u];
 #pragma unroll
-            for (int m = SEG; m >= 1; --m)
-                if (m <= deg) O[m] = fmaT(vu, O[m - 1], O[m]);
+                for (int m = SEG; m >= 1; --m)
+                    if (m <= u + 1) P[m] = fmaT(vu, P[m - 1], P[m]);
+            }
         }
-        double K[GB];
+        double G[GB];
 #pragma unroll
         for (int a2 = 0; a2 < GB; ++a2) {
             double acc = 0.0;
 #pragma unroll
-            for (int c = 0; c <= SEG; ++c)
-                if (a2 < nb && c + nb <= SEG) acc = fmaT(O[c], H[a2 + c < SEG ? a2 + c : 0], acc);
-            K[a2] = acc;
+            for (int i = 0; i <= SEG; ++i)
+                if (a2 < nb && i <= lo) acc = fmaT(P[i], H[a2 + i < SEG ? a2 + i : 0], acc);
+            G[a2] = acc;
         }
 #pragma unroll
-        for (int t = 0; t < GB; ++t) {
-            if (t < nb) {
-                double E[GB];
-                E[0] = 1.0;
+        for (int tl = GB - 1; tl >= 0; --tl) {
+            if (tl < nb) {
+                double Q[GB];
+                Q[0] = 1.0;
 #pragma unroll
-                for (int m = 1; m < GB; ++m) E[m] = 0.0;
+                for (int m = 1; m < GB; ++m) Q[m] = 0.0;
 #pragma unroll
                 for (int u = 0; u < GB; ++u) {
-                    if (u < nb && u != t) {
-                        const int deg = u < t ? u + 1 : u;   // positions of the block before u, t excluded
+                    if (u < tl) {
                         const double vu = (double)v[lo + u < SEG ? lo + u : 0];
 #pragma unroll
                         for (int m = GB - 1; m >= 1; --m)
-                            if (m <= deg) E[m] = fmaT(vu, E[m - 1], E[m]);
+                            if (m <= u + 1) Q[m] = fmaT(vu, Q[m - 1], Q[m]);
                     }
                 }
                 double g = 0.0;
 #pragma unroll
-                for (int a2 = 0; a2 < GB; ++a2)
-                    if (a2 < nb) g = fmaT(E[a2], K[a2], g);
-                out(lo + t, g);
+                for (int i = 0; i < GB; ++i)
+                    if (i <= tl) g = fmaT(Q[i], G[i], g);
+                out(lo + tl, g);
+                const double vt = (double)v[lo + tl < SEG ? lo + tl : 0];
+#pragma unroll
+                for (int i = 0; i < GB - 1; ++i)
+                    if (i < tl) G[i] = fmaT(vt, G[i + 1], G[i]);
+            }
+        }
+        // R for the previous block: the moments taken through this block too
+#pragma unroll
+        for (int u = 0; u < GB; ++u) {
+            if (bi > 0 && u < nb) {
+                const double vu = (double)v[lo + u < SEG ? lo + u : 0];
+                const int len = hi - u;
+#pragma unroll
+                for (int q = 0; q < SEG - 1; ++q)
+                    if (q < len - 1) H[q] = fmaT(vu, H[q + 1], H[q]);
             }
         }
     }

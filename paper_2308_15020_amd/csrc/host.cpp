@@ -449,15 +449,18 @@ TypeD uc_type(const std::vector<cld> &ft, int k, int L, int s)
 // lanes (6 log2 L), the quotient by the segment product (16, none on one
 // lane), the moments' coefficients (6) and the value term (5), and the
 // moments (s FMAs and (s+1)/2 - 1 powers of -tau^2); per lane once, the
-// gradients from the moments in blocks of 8 positions.
+// gradients from the moments (about 2 s^2 FMAs, seg_grad_from_moments).
 double poly_flops(int s, int L, int nf)
 {
     int lg = 0;
     while ((1 << lg) < L) ++lg;
-    double tail = 0.0;
+    double tail = 0.0;   // FMAs of the gradient pass (seg_grad_from_moments)
     for (int lo = 0; lo < s; lo += 8) {
-        const int nb = std::min(8, s - lo), out = s - nb;
-        tail += 0.5 * out * (out + 1) + (double)nb * (out + 1) + nb * (0.5 * (nb - 1) * nb + nb);
+        const int nb = std::min(8, s - lo), hi = lo + nb;
+        tail += 0.5 * lo * (lo + 1) + (double)nb * (lo + 1);
+        for (int t = 0; t < nb; ++t) tail += 0.5 * t * (t + 1) + (t + 1) + t;
+        if (lo > 0)
+            for (int u = 0; u < nb; ++u) tail += hi - u - 1;
     }
     const double per_freq = 4.0 * s + (s + 1) / 2 - 1 + 13.0 + (L > 1 ? 16.0 : 0.0) + 6.0 * lg;
     return (double)L * ((double)s * (s + 1) + (double)nf * per_freq + 2.0 * tail);
