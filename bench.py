@@ -198,22 +198,31 @@ def measure(name, args, dev, headline):
             "U": torch.empty(inst.m, dtype=torch.int32, device=dev)}
 
     # eager loop: objective, gradient, exact check of x_t and the projected
-    # step in one pass, then the adaptive weights; library events per kernel
+    # step in one pass, then the adaptive weights; library events per kernel.
+    # Each kernel's own launch time: the same tuned plan (launch structure and
+    # shapes from the tuner's cache) with every launch on one stream, so that
+    # concurrent launches do not stretch each other's events
+    tplan = plan if args.serial else Plan(prob, B, autotune=not args.no_autotune, tune_cache=args.tune_cache,
+                                          side_streams=False, mode=args.mode,
+                                          persistent=wl.get("persistent", False))
+
     def eager_step():
-        o = plan.eval_step(x, args.eta)
-        plan.erwa_update(o["U"], 0.4)
+        o = tplan.eval_step(x, args.eta)
+        tplan.erwa_update(o["U"], 0.4)
 
     prof_steps = max(1, min(steps, 10))
     for _ in range(max(1, warmup // 2)):
         eager_step()
     torch.cuda.synchronize()
-    plan.profile(True)
-    plan.profile_read(reset=True)
+    tplan.profile(True)
+    tplan.profile_read(reset=True)
     for _ in range(prof_steps):
         eager_step()
     torch.cuda.synchronize()
-    prof = plan.profile_read(reset=True)
-    plan.profile(False)
+    prof = tplan.profile_read(reset=True)
+    tplan.profile(False)
+    if tplan is not plan:
+        tplan.close()
 
     # timed loop: chunk fused iterations per graph replay
     # the persistent loop runs every timed iteration in one launch
