@@ -202,8 +202,10 @@ def measure(name, args, dev, headline):
     # Each kernel's own launch time: the same tuned plan (launch structure and
     # shapes from the tuner's cache) with every launch on one stream, so that
     # concurrent launches do not stretch each other's events
+    d0 = plan.describe()
     tplan = plan if args.serial else Plan(prob, B, autotune=not args.no_autotune, tune_cache=args.tune_cache,
-                                          side_streams=False, mode=args.mode,
+                                          side_streams=False, mode=d0["mode"],
+                                          pull={0: "off", 3: "le3", 7: "le7"}.get(d0["pull"], "auto"),
                                           persistent=wl.get("persistent", False))
 
     def eager_step():
@@ -221,6 +223,7 @@ def measure(name, args, dev, headline):
     torch.cuda.synchronize()
     prof = tplan.profile_read(reset=True)
     tplan.profile(False)
+    tdesc = tplan.describe()   # its bins are the profile's bin indices
     if tplan is not plan:
         tplan.close()
 
@@ -246,7 +249,8 @@ def measure(name, args, dev, headline):
     n_sat_last = int(outs["n_sat"].max().item())
 
     desc = plan.describe()
-    bins = desc["bins"]["f32"]
+    bins = tdesc["bins"]["f32"]
+    assert tdesc["mode"] == desc["mode"] and len(tdesc["bins"]["f32"]) == len(desc["bins"]["f32"])
     kern = [k for k in prof["kernels"] if k["io"] == "f32"]
     entries = []
     for k in kern:
@@ -270,6 +274,7 @@ def measure(name, args, dev, headline):
                      f"len <= {max(b['maxk'] for b in grp)})")
             ent = roofline_entry(label, flop, nbytes, "f64", avg_s, per_step)
             ent["flop_exact_per_launch"] = sum(bin_flop_exact(b, B) for b in grp)
+            ent["flop_10k2_per_launch"] = sum(FLOP_PER_K2 * b["k2_per_restart"] * B for b in grp)
             ent["kernel_name"] = "k_eval_group64"
         elif k["bin"] >= 0:
             bd = bins[k["bin"]]
@@ -278,6 +283,8 @@ def measure(name, args, dev, headline):
                      f"{bd['count']} constraints, len <= {bd['maxk']})")
             ent = roofline_entry(label, flop, nbytes, dt, avg_s, per_step)
             ent["flop_exact_per_launch"] = bin_flop_exact(bd, B)
+            if bd["ct"] == "f64" and bd["class"] == "dft":
+                ent["flop_10k2_per_launch"] = FLOP_PER_K2 * bd["k2_per_restart"] * B
             ent["kernel_name"] = (f"k_eval<float, {'double' if bd['ct'] == 'f64' else 'float'}, {bd['seg']}, "
                                   f"{bd['L']}, {'true' if bd['class'] == 'dft' else 'false'}>")
         elif k["bin"] == -3:
@@ -312,11 +319,13 @@ def measure(name, args, dev, headline):
             merged[e["kernel_name"]] = dict(e, _t=e["avg_launch_ms"] * e["launches_per_step"], _f=e["flop_per_launch"]
                                             * e["launches_per_step"], _b=e["bytes_per_launch"] * e["launches_per_step"],
                                             _x=e.get("flop_exact_per_launch", 0.0) * e["launches_per_step"],
+                                            _k=e.get("flop_10k2_per_launch", 0.0) * e["launches_per_step"],
                                             _n=e["launches_per_step"], parts=1)
         else:
             m["_t"] += e["avg_launch_ms"] * e["launches_per_step"]
             m["_f"] += e["flop_per_launch"] * e["launches_per_step"]
             m["_x"] += e.get("flop_exact_per_launch", 0.0) * e["launches_per_step"]
+            m["_k"] += e.get("flop_10k2_per_launch", 0.0) * e["launches_per_step"]
             m["_b"] += e["bytes_per_launch"] * e["launches_per_step"]
             m["_n"] += e["launches_per_step"]
             m["parts"] += 1
@@ -330,6 +339,8 @@ def measure(name, args, dev, headline):
         if m["_x"] > 0 and ent["bound"] == "alu":
             ent["flop_exact_per_launch"] = m["_x"] / n
             ent["frac_exact"] = m["_x"] / n / (m["_t"] / n / 1e3) / 1e12 / PEAK_TFLOPS[m["arith"]]
+        if m["_k"] > 0:
+            ent["flop_10k2_per_launch"] = m["_k"] / n
         kernels.append(ent)
     # the FP64 root-of-unity bins launched one per segment shape (per-bin
     # launch structure) run one kernel template in several instances: they
@@ -346,11 +357,18 @@ def measure(name, args, dev, headline):
                              f"{len(fam)} segment shapes)", f / n, nb / n, "f64", t / n / 1e3, n)
         ent["kernel_name"] = FP64_FAMILY
         ent["ms_per_step"] = t
+        k10 = sum(e.get("flop_10k2_per_launch", 0.0) * e["launches_per_step"] for e in fam)
+        if k10 > 0:
+            ent["flop_10k2_per_launch"] = k10 / n
         ent["members"] = [e["kernel_name"] for e in fam]
         kernels = [e for e in kernels if e not in fam] + [ent] + fam
     kernels.sort(key=lambda e: -e["ms_per_step"])
     top = [e for e in kernels if not any(e["kernel_name"] in k.get("members", ()) for k in kernels)]
     dom = dict(top[0])
+    if "flop_10k2_per_launch" in dom:
+        # the same work at the 10 k^2 pricing of the running products: a rate
+        # above the FP64 peak shows how much less the polynomial form computes
+        dom["tflops_at_10k2"] = dom["flop_10k2_per_launch"] / (dom["avg_launch_ms"] / 1e3) / 1e12
     dom["traffic"] = None
     card = kernel_card(name, dom["kernel_name"])
     if card is not None:
