@@ -14,7 +14,10 @@
 //     (prefix inside its segment) * (product of earlier segments)
 //   * (product of later segments) * (suffix inside its segment),
 // the segment products being exchanged by exclusive prefix/suffix scans
-// over the L lanes (DPP row shifts for L <= 16).  Constraint descriptors and
+// over the L lanes (DPP row shifts for L <= 16).  FP64 root-of-unity bins
+// evaluate each segment's product as a polynomial in the frequency's factor
+// coefficient and accumulate per-degree moments for the gradient (the
+// polynomial form, below).  Constraint descriptors and
 // coefficient tables are wave-uniform (scalar loads, the next frequency's
 // entry prefetched); literal values are gathered from x[v][b] with restarts
 // contiguous, so a wave reads 64/L consecutive restarts of a variable per
@@ -295,31 +298,22 @@ __device__ __forceinline__ double recip_f64(double v)
 // reverse traversal that adds Re(c1 * leave-one-out product) to every
 // position's gradient.  FORM 1: psi = 1 - i tk l; FORM 2: psi = tk - i l;
 // FORM 3 (the unit-circle form of Eq. forward): psi = (tk + l) + i p0 with
-// (tk, p0) = (cos, sin) of the frequency's root, so that c1 = c0.
+// (tk, p0) = (cos, sin) of the frequency's root, so that c1 = c0.  FP32
+// bins and the unit-circle form; FP64 bounded-basis bins take the polynomial
+// form below.  The other lanes' products come from exclusive scans.
 template <typename CT, int SEG, int L, int FORM>
 __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (&gr)[SEG], const FreqT<CT> &fr,
                                           CT &we)
 {
-    // FP64 bounded-basis frequencies over several lanes: whole product by a
-    // butterfly, then a division (no scans)
-    constexpr bool ALLRED = sizeof(CT) == 8 && L >= 2 && FORM != 3;
-    // FP64 form-1 factors in 32-lane groups (segments of at most 16): the
-    // reverse pass reuses the forward pass's tau * l (2 more VGPRs per
-    // position, one FP64 multiply less per position and frequency); these
-    // kernels run at 2 waves per SIMD either way, narrower groups would drop
-    // from 3 to 2
-    constexpr bool KEEP_U = sizeof(CT) == 8 && FORM == 1 && SEG <= 16 && L == 32;
-    (void)j;
+    static_assert(sizeof(CT) == 4 || FORM == 3, "FP64 bounded-basis bins use freq_pass_poly");
     const CT tk = fr.tk;
     CT pr[SEG], pi[SEG];
-    CT uk[KEEP_U ? SEG : 1];
     CT Pr = fr.init, Pi = 0;
 #pragma unroll
     for (int t = 0; t < SEG; ++t) {
         pr[t] = Pr; pi[t] = Pi;
         if constexpr (FORM == 1) {
             const CT u = tk * lv[t];
-            if constexpr (KEEP_U) uk[t] = u;
             const CT nr = fmaT(Pi, u, Pr);
             const CT ni = fmaT(-Pr, u, Pi);
             Pr = nr; Pi = ni;
@@ -335,29 +329,14 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
             Pr = nr; Pi = ni;
         }
     }
-    CT qr, qi;   // product of the other lanes' segments (exclusive prefix times exclusive suffix)
-    if constexpr (ALLRED) {
-        // FP64: every lane forms the whole product with a butterfly and
-        // divides its own segment out.  FP64 products of at most 16
-        // bounded factors stay far from underflow, so the division is
-        // safe; it replaces two 32-lane scans per frequency.
-        CT Tr = Pr, Ti = Pi;
-        allreduce_prod_f64<L>(Tr, Ti);
-        we += fmaT(fr.c0re, Tr, -fr.c0im * Ti);
-        const CT nrm = fmaT(Pr, Pr, Pi * Pi);
-        const CT rinv = recip_f64(nrm);
-        const CT ir = Pr * rinv, ii = -Pi * rinv;
-        qr = fmaT(Tr, ir, -Ti * ii);
-        qi = fmaT(Tr, ii, Ti * ir);
-    } else {
-        CT er, ei, sr, si;
-        group_scan_cplx<CT, L>(j, Pr, Pi, er, ei, sr, si);
-        const CT Gr = fmaT(Pr, sr, -Pi * si);
-        const CT Gi = fmaT(Pr, si, Pi * sr);
-        we += fmaT(fr.c0re, Gr, -fr.c0im * Gi);
-        qr = fmaT(er, sr, -ei * si);
-        qi = fmaT(er, si, ei * sr);
-    }
+    // product of the other lanes' segments (exclusive prefix times exclusive suffix)
+    CT er, ei, sr, si;
+    group_scan_cplx<CT, L>(j, Pr, Pi, er, ei, sr, si);
+    const CT Gr = fmaT(Pr, sr, -Pi * si);
+    const CT Gi = fmaT(Pr, si, Pi * sr);
+    we += fmaT(fr.c0re, Gr, -fr.c0im * Gi);
+    const CT qr = fmaT(er, sr, -ei * si);
+    const CT qi = fmaT(er, si, ei * sr);
     // the factors are recomputed from an opaque copy of tk so that the
     // forward products are not kept alive across both passes
     CT tkb = tk;
@@ -369,9 +348,7 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
         gr[t] = fmaT(pr[t], Sr, fmaT(-pi[t], Si, gr[t]));
         if (t > 0) {
             if constexpr (FORM == 1) {
-                CT u;
-                if constexpr (KEEP_U) u = uk[t];
-                else u = tkb * lv[t];
+                const CT u = tkb * lv[t];
                 const CT nr = fmaT(Si, u, Sr);
                 const CT ni = fmaT(-Sr, u, Si);
                 Sr = nr; Si = ni;
