@@ -87,7 +87,7 @@ def test_profsum_family_card(tmp_path):
     assert "family" in profsum.trace(str(trace))
 
 
-@pytest.mark.parametrize("workload,kernel", [("large", "k_eval<float, double, *, *, true>"),
+@pytest.mark.parametrize("workload,kernel", [("large", "k_eval_group64"),
                                              ("large3sat", "k_pull<4, 4, true>"),
                                              ("mixed2000", "k_eval_group")])
 def test_committed_cards_cover_dominant_kernels(workload, kernel):
