@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 
 // The root-of-unity bins with FP64 arithmetic (k >= 128 by default) in one
 // grid as well: the ramp and tail of a launch are paid once instead of once
-// per bin.  (SEG, L): 14..32 at L = 16, 16, 20 and 24 at L = 8.  Compiled for
+// per bin.  (SEG, L): 14..32 at L = 16, 16, 20, 24 and 25..32 at L = 8.  Compiled for
 // 3 waves per SIMD (168 VGPRs): the variants of more than 28 positions spill
 // a few per-constraint values, none in their frequency loops, and the grid
 // runs 20% faster than at the 2 waves their full register count would give.
@@ -77,7 +77,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     X(0, 17, 16) X(1, 18, 16) X(2, 19, 16) X(3, 20, 16) X(4, 21, 16) X(5, 22, 16) X(6, 23, 16)           \
     X(7, 24, 16) X(8, 25, 16) X(9, 26, 16) X(10, 27, 16) X(11, 28, 16) X(12, 29, 16) X(13, 30, 16)       \
     X(14, 31, 16) X(15, 32, 16) X(16, 14, 16) X(17, 15, 16) X(18, 16, 16) X(19, 16, 8) X(20, 20, 8)      \
-    X(21, 24, 8)
+    X(21, 24, 8) X(22, 25, 8) X(23, 26, 8) X(24, 27, 8) X(25, 28, 8) X(26, 29, 8) X(27, 30, 8)          \
+    X(28, 31, 8) X(29, 32, 8)
 
 int group_variant64(int seg, int L)
 {

@@ -869,8 +869,8 @@ struct EvalFn {
 
 // Segment shapes.  FP32 arithmetic: L = 1 with SEG in {4, 8, ..., 32}, L >= 2
 // with SEG in {16, 20, 24, 28, 32}.  FP64 arithmetic: L = 1 with SEG in
-// {4, 8, ..., 24}; L = 2..8 with SEG in {16, 20, 24}; L = 16 with every SEG
-// from 14 to 32 (the long root-of-unity bins: a padding position costs as
+// {4, 8, ..., 24}; L = 2..8 with SEG in {16, 20, 24}, L = 8 also with every
+// SEG from 25 to 32; L = 16 with every SEG from 14 to 32 (the long root-of-unity bins: a padding position costs as
 // much as a literal in every frequency, and in the polynomial form the
 // per-frequency cost of a lane, about 2.5 SEG operations plus a butterfly
 // stage per doubling of L, favours long segments; 32 positions still fit 2
@@ -903,14 +903,14 @@ static EvalFn<IO> pick_L(int seg)
     case 22: if constexpr (F64 && L == 16) return handle<IO, CT, 22, L, CPLX>(); break;
     case 23: if constexpr (F64 && L == 16) return handle<IO, CT, 23, L, CPLX>(); break;
     case 24: if constexpr (!F64 || L <= 16) return handle<IO, CT, 24, L, CPLX>(); break;
-    case 25: if constexpr (F64 && L == 16) return handle<IO, CT, 25, L, CPLX>(); break;
-    case 26: if constexpr (F64 && L == 16) return handle<IO, CT, 26, L, CPLX>(); break;
-    case 27: if constexpr (F64 && L == 16) return handle<IO, CT, 27, L, CPLX>(); break;
-    case 28: if constexpr (!F64 || L == 16) return handle<IO, CT, 28, L, CPLX>(); break;
-    case 29: if constexpr (F64 && L == 16) return handle<IO, CT, 29, L, CPLX>(); break;
-    case 30: if constexpr (F64 && L == 16) return handle<IO, CT, 30, L, CPLX>(); break;
-    case 31: if constexpr (F64 && L == 16) return handle<IO, CT, 31, L, CPLX>(); break;
-    case 32: if constexpr (!F64 || L == 16) return handle<IO, CT, 32, L, CPLX>(); break;
+    case 25: if constexpr (F64 && (L == 8 || L == 16)) return handle<IO, CT, 25, L, CPLX>(); break;
+    case 26: if constexpr (F64 && (L == 8 || L == 16)) return handle<IO, CT, 26, L, CPLX>(); break;
+    case 27: if constexpr (F64 && (L == 8 || L == 16)) return handle<IO, CT, 27, L, CPLX>(); break;
+    case 28: if constexpr (!F64 || L == 8 || L == 16) return handle<IO, CT, 28, L, CPLX>(); break;
+    case 29: if constexpr (F64 && (L == 8 || L == 16)) return handle<IO, CT, 29, L, CPLX>(); break;
+    case 30: if constexpr (F64 && (L == 8 || L == 16)) return handle<IO, CT, 30, L, CPLX>(); break;
+    case 31: if constexpr (F64 && (L == 8 || L == 16)) return handle<IO, CT, 31, L, CPLX>(); break;
+    case 32: if constexpr (!F64 || L == 8 || L == 16) return handle<IO, CT, 32, L, CPLX>(); break;
     default: break;
     }
     return EvalFn<IO>{};

@@ -479,8 +479,9 @@ void shape_for_uc(int k, int &seg, int &L)
 // positions each, L * SEG >= k, the smallest such L and then the smallest
 // SEG.  FP32 arithmetic: SEG in {4, 8, 16, 24} (32 past k = 384); products
 // at roots of unity (dft) also take 12 on one lane and 20 on several.  FP64
-// arithmetic: SEG up to 24 (multiples of 4 below 16 lanes), 16-lane groups
-// take every SEG from 14 to 32 (k <= 512): in root-of-unity bins a padding
+// arithmetic: SEG up to 24 (multiples of 4 below 8 lanes and up to 24 at 8),
+// 8-lane groups take every SEG from 25 to 32 (k <= 256) and 16-lane groups
+// every SEG from 14 to 32 (k <= 512): in root-of-unity bins a padding
 // position costs as much as a literal in every frequency, and each doubling
 // of L adds a butterfly stage per frequency.  Real chains pay for padding once, so they keep the coarser
 // steps: fewer distinct shapes mean fewer, larger kernel launches.
@@ -488,12 +489,14 @@ void shape_for(int ct, int k, int &seg, int &L, bool dft)
 {
     if (ct == CT_F64) {
         L = 1;
-        while ((k + L - 1) / L > 24 && L < 16) L <<= 1;
-        // 16 lanes of up to 32 positions (k <= 512); longer constraints have
-        // no FP64 variant (32 lanes)
+        while ((k + L - 1) / L > 24 && L < 8) L <<= 1;
+        // 8 lanes of up to 32 positions (k <= 256), then 16 lanes of up to 32
+        // (k <= 512); longer constraints have no FP64 variant (32 lanes)
+        if (L == 8 && (k + 7) / 8 > 32) L = 16;
         if (L == 16 && (k + 15) / 16 > 32) L = 32;
         const int s = (k + L - 1) / L;
         if (L >= 16) seg = std::max(14, s);   // every count: padding costs as much as a literal
+        else if (L == 8 && s > 24) seg = s;
         else if (L > 1) seg = std::max(16, ((s + 3) / 4) * 4);
         else seg = s <= 4 ? 4 : ((s + 3) / 4) * 4;
         return;

@@ -16,7 +16,7 @@ TOL64 = 1e-12
 def every_bin_instance(seed=11, n=700):
     """Short and long constraints of every kind: all segment counts of the
     FP32 and FP64 kernels (FP64 root-of-unity shapes 14..32 positions over
-    16 lanes, 16..24 over 8), thresholds outside [1, k], length-1
+    16 lanes, 16..32 over 8), thresholds outside [1, k], length-1
     constraints."""
     base = random_hybrid(n, seed, n_or=150, or_len=(1, 9), n_xor=60, xor_len=(1, 40),
                          n_card=70, card_len=(1, 140), card_t=(0, 70), weights="uniform")
@@ -27,7 +27,8 @@ def every_bin_instance(seed=11, n=700):
                        (2, 64, 64), (2, 65, 1), (2, 33, 34), (0, 17, 0), (1, 64, 1),
                        (2, 340, 170), (2, 384, 1), (2, 449, 224), (2, 180, 90), (2, 47, 20), (1, 46, 1),
                        (2, 430, 215), (2, 441, 100), (2, 470, 235), (2, 490, 17), (2, 128, 64),
-                       (2, 150, 75), (2, 161, 3)]:
+                       (2, 150, 75), (2, 161, 3), (2, 206, 50), (2, 220, 110), (2, 230, 5), (2, 240, 120),
+                       (2, 248, 124)]:
         v = rng.choice(n, size=k, replace=False) + 1
         sg = np.where(rng.random(k) < 0.5, -1, 1)
         extra.append((kind, [t], [(v * sg).astype(np.int32)]))
