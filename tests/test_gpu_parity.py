@@ -96,6 +96,37 @@ def test_eval_f64_every_bin(ffs, mixed, dist):
     assert e["con_val"] <= TOL64 and e["F"] <= TOL64 and e["grad"] <= TOL64, e
 
 
+@pytest.mark.parametrize("fg", [2, 4])
+def test_fp64_frequency_split(ffs, mixed, tmp_path, fg):
+    """Per-bin FP64 root-of-unity launches with each constraint's frequencies
+    split over fg waves of a workgroup (the waves' moments added through LDS
+    in wave order before the gradient pass), forced through the tune cache:
+    values and gradients against the oracle."""
+    import json
+    inst, prob = mixed
+    B = 64
+    cache = str(tmp_path / "tune.json")
+    ffs.Plan(prob, B, autotune=True, tune_cache=cache, mode="per_bin").close()
+    c = json.load(open(cache))
+    keys = [k for k in c if "|c1|t1|" in k]   # root-of-unity class, FP64 arithmetic
+    assert keys
+    for k in keys:
+        c[k] = [1, 1, fg]
+    json.dump(c, open(cache, "w"))
+    plan = ffs.Plan(prob, B, autotune=True, tune_cache=cache, mode="per_bin")
+    d = plan.describe()
+    f64 = [b for b in d["bins"]["f32"] if b["ct"] == "f64" and b["class"] == "dft"]
+    assert f64 and all(b["fg"] == fg for b in f64)
+    for dist in ("uniform", "near_corner"):
+        x = points(inst, B, 55, dist)
+        g = _gpu_eval(plan, x)
+        ref = oracle.eval_batch(inst, x.astype(np.float64), want_con=True)
+        e = errors(inst, g, ref)
+        print(fg, dist, e)
+        assert e["con_val"] <= TOL32 and e["F"] <= TOL32 and e["grad"] <= TOL32, e
+    plan.close()
+
+
 def test_force_dft_matches_closed_forms(ffs):
     """OR and XOR through the root-of-unity path against the closed forms."""
     inst = workloads.random_hybrid(600, 5, n_or=120, or_len=(1, 64), n_xor=120, xor_len=(1, 300),
