@@ -216,7 +216,10 @@ ffsat_status ffsat_plan_profile_read(ffsat_plan *plan, int32_t reset, char *buf,
  * coefficients) and differentiated by leave-one-out prefix/suffix products
  * (Eq. chain); OR and XOR use the transform-free products (App. B).
  * Computation is FP32 except the root-of-unity products of constraints at
- * least fp64_min_len long, which run in FP64.  Results are deterministic
+ * least fp64_min_len long, which run in FP64; there each lane's segment
+ * product at a root is evaluated from the segment's elementary symmetric
+ * polynomials and the leave-one-out products through per-degree moments
+ * (the same quantities in another rounding order).  Results are deterministic
  * (no floating-point atomics).  Points outside [-1,1] are evaluated as
  * given (the polynomial is defined everywhere). */
 ffsat_status ffsat_eval(ffsat_plan *plan, const float *x, float *F, float *grad,
