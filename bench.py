@@ -199,14 +199,18 @@ def measure(name, args, dev, headline):
 
     # eager loop: objective, gradient, exact check of x_t and the projected
     # step in one pass, then the adaptive weights; library events per kernel.
-    # Each kernel's own launch time: the same tuned plan (launch structure and
-    # shapes from the tuner's cache) with every launch on one stream, so that
-    # concurrent launches do not stretch each other's events
+    # With one launch per bin (many launches overlapping on the side
+    # streams) each kernel's own launch time comes from the same tuned plan
+    # with every launch on one stream (the per-bin shapes come from the
+    # tuner's cache, a fixed per-bin structure times nothing more), so that
+    # concurrent launches do not stretch each other's events; a grouped
+    # structure is timed as it runs.
     d0 = plan.describe()
-    tplan = plan if args.serial else Plan(prob, B, autotune=not args.no_autotune, tune_cache=args.tune_cache,
-                                          side_streams=False, mode=d0["mode"],
-                                          pull={0: "off", 3: "le3", 7: "le7"}.get(d0["pull"], "auto"),
-                                          persistent=wl.get("persistent", False))
+    split = not args.serial and d0["mode"] == "per_bin"
+    tplan = plan if not split else Plan(prob, B, autotune=not args.no_autotune, tune_cache=args.tune_cache,
+                                        side_streams=False, mode="per_bin",
+                                        pull={0: "off", 3: "le3", 7: "le7"}.get(d0["pull"], "auto"),
+                                        persistent=wl.get("persistent", False))
 
     def eager_step():
         o = tplan.eval_step(x, args.eta)
