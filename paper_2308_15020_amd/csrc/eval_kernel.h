@@ -306,14 +306,19 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
                                           CT &we)
 {
     static_assert(sizeof(CT) == 4 || FORM == 3, "FP64 bounded-basis bins use freq_pass_poly");
+    // form-1 segments of at most 16: the reverse pass reuses the forward
+    // pass's tau * l (SEG more VGPRs, one multiply less per position)
+    constexpr bool KEEP_U = FORM == 1 && SEG <= 16;
     const CT tk = fr.tk;
     CT pr[SEG], pi[SEG];
+    CT uk[KEEP_U ? SEG : 1];
     CT Pr = fr.init, Pi = 0;
 #pragma unroll
     for (int t = 0; t < SEG; ++t) {
         pr[t] = Pr; pi[t] = Pi;
         if constexpr (FORM == 1) {
             const CT u = tk * lv[t];
+            if constexpr (KEEP_U) uk[t] = u;
             const CT nr = fmaT(Pi, u, Pr);
             const CT ni = fmaT(-Pr, u, Pi);
             Pr = nr; Pi = ni;
@@ -348,7 +353,7 @@ __device__ __forceinline__ void freq_pass(const int j, const CT (&lv)[SEG], CT (
         gr[t] = fmaT(pr[t], Sr, fmaT(-pi[t], Si, gr[t]));
         if (t > 0) {
             if constexpr (FORM == 1) {
-                const CT u = tkb * lv[t];
+                const CT u = KEEP_U ? uk[t] : tkb * lv[t];
                 const CT nr = fmaT(Si, u, Sr);
                 const CT ni = fmaT(-Sr, u, Si);
                 Sr = nr; Si = ni;
