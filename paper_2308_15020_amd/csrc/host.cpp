@@ -161,7 +161,8 @@ static std::vector<float> rkind_table()
 // of every segment are folded into c0 / c1 here, in long double.
 //
 // FP64 tables (f64 = true) run every frequency with form 1's factor (the
-// polynomial form evaluates at z = -i tau): a form-2 factor is
+// polynomial form evaluates at z = -i tau), FP32 tables of segments of at
+// most 16 too where the start value stays above 1e-30: a form-2 factor is
 // kappa (1 - i l / kappa), kappa = C/S, so its lane takes tau = S/C and
 // starts from kappa^s times the usual start value; each segment product is
 // then exactly the form-2 one (FP64 holds kappa^s, >= 1e-81 for k <= 512 and
@@ -195,7 +196,12 @@ TypeD dft_type(const std::vector<cld> &hv, int k, int L, int s, bool f64)
         for (int q = 0; q < npad; ++q) corr /= psipad;
         const cld c0 = 2.0L * h * sigma * corr * ldexpl(1.0L, L * e);
         const cld c1 = c0 * (form1 ? cld(0.0L, -tk) : cld(0.0L, -1.0L));
-        if (f64 && !form1) {
+        // FP32 takes the same route where its range allows: segments of at
+        // most 16 (the kernels keep tau * l for the reverse pass there, so a
+        // factor costs 3 + 4 operations instead of 4 + 6) and a start value
+        // far inside the normal range
+        const bool via1 = f64 || (s <= 16 && ldexpl(1.0L, -e) * powl(tk, (long double)s) >= 1e-30L);
+        if (via1 && !form1) {
             // form 2 through form 1's code (see above)
             const cld c1r = c1 / tk;
             FreqD fd{(double)(1.0L / tk), (double)(ldexpl(1.0L, -e) * powl(tk, (long double)s)), (double)c0.real(),
